@@ -1,0 +1,182 @@
+/*
+ * cube.h -- C ABI of libcube: the hot path of CUBE's information-optimised particle-mesh step
+ * (Yu, Pen & Wang, "CUBE: An Information-optimized parallel Cosmological N-body Algorithm",
+ * arXiv:1712.06121) on one AMD Instinct MI355X (gfx950).
+ *
+ * Particles are stored as in Sec. 2.1-2.2 of the paper: a 1- or 2-byte position code per
+ * dimension relative to the coarse cell that holds the particle (Eqs. (chi), (x)), a 1- or
+ * 2-byte velocity code per dimension relative to the coarse-cell mean velocity (Eqs. (nu), (v)),
+ * per-cell counts and cell-ordered storage. One step decodes, deposits the mass by cloud-in-cell,
+ * solves Poisson's equation by FFT, interpolates the force, kicks and drifts, re-encodes and
+ * re-orders the particles by coarse cell (Sec. 2.3.3, Figs. code, update_xp, update_vp).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns CUBE_OK (0) or a negative CUBE_E_* code and never throws. The text of
+ *   the last error of a simulation is returned by cube_last_error().
+ * - Device work is enqueued on the stream given at creation (a hipStream_t; NULL = the null
+ *   stream). Calls that take host buffers synchronise that stream before returning.
+ * - The simulation owns all device memory it allocates (through the allocator callback when
+ *   one is given, hipMalloc otherwise). The caller owns every host buffer it passes.
+ * - One simulation must not be used by two host threads at the same time.
+ * - Mesh and coarse-cell arrays are x-fastest: cell id c = x + N (y + N z).
+ * - Units: lengths in fine-mesh cells, H0 = 1, momentum p = a^2 dx/dt (fine cells x H0).
+ *   Mesh-to-coarse ratio R = nm_side / nc_side must be 4 (the paper's usual choice, Sec. 2.3.1).
+ */
+#ifndef CUBE_H
+#define CUBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------------ */
+#define CUBE_OK 0
+#define CUBE_DONE 1            /* cube_step reached a_final (not an error)                     */
+#define CUBE_E_INVALID -1      /* bad argument or parameter combination                        */
+#define CUBE_E_NOMEM -2        /* device or host allocation failed                             */
+#define CUBE_E_DEVICE -3       /* a HIP runtime call failed                                    */
+#define CUBE_E_CAPACITY -4     /* a particle count exceeds the capacity fixed at creation      */
+#define CUBE_E_CFL -5          /* a particle moved more than one coarse cell in one step       */
+#define CUBE_E_NONFINITE -6    /* a non-finite position or velocity appeared                   */
+#define CUBE_E_OVERFLOW -7     /* an integer accumulator would overflow                        */
+#define CUBE_E_STATE -8        /* call out of order (e.g. step before any particles exist)     */
+
+#define CUBE_SIGMA_GLOBAL 0    /* one dispersion for the whole box (Sec. 2.2, last paragraph)  */
+#define CUBE_SIGMA_PER_CELL 1  /* per-coarse-cell dispersion, global value as fallback         */
+
+typedef struct cube_sim cube_sim;
+
+/* Simulation parameters. Cosmology follows Sec. 2.2 (a, H, D, f); the initial conditions
+ * follow Sec. 2.3.2: BBKS transfer function with shape Omega_m h, spectral index n_s, amplitude
+ * fixed by sigma_8, Zel'dovich displacement at a_init. The schedule has n_steps steps between
+ * a_init and a_final, uniform in ln a (spacing 0) or in a (spacing 1), integrated as DKD
+ * leapfrog with merged drifts -- the paper's (DKKD)^n with the last half drift at the end. */
+typedef struct {
+  int32_t np_side;      /* particles per side of the initial lattice (N_p = np_side^3)          */
+  int32_t nm_side;      /* fine mesh cells per side; a power of two, 32 .. 2048                 */
+  int32_t nc_side;      /* coarse cells per side; nm_side / 4                                   */
+  int32_t x_bytes;      /* n_chi in {1, 2}: bytes per position code and dimension, Eq. (chi)    */
+  int32_t v_bytes;      /* n_nu in {1, 2}: bytes per velocity code and dimension, Eq. (nu)      */
+  int32_t sigma_mode;   /* CUBE_SIGMA_GLOBAL or CUBE_SIGMA_PER_CELL                             */
+  int32_t n_steps;      /* number of leapfrog steps from a_init to a_final                      */
+  int32_t spacing;      /* 0: uniform in ln a, 1: uniform in a                                   */
+  double box;           /* box side L in Mpc/h                                                   */
+  double omega_m, omega_l, h, sigma8, n_s;
+  double a_init, a_final;
+  uint64_t seed;        /* seed of the Philox4x32-10 white-noise stream                          */
+  int64_t capacity;     /* maximum particle count; 0 means np_side^3                             */
+} cube_params;
+
+/* Optional device allocator (e.g. a framework's caching allocator). alloc returns a device
+ * pointer of at least `bytes` bytes aligned to 256 bytes, or NULL; free releases it. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} cube_allocator;
+
+/* Create a simulation on the current HIP device. `stream` is a hipStream_t or NULL; `alloc`
+ * may be NULL. Builds the FFT plans, the codec tables and the time-step schedule (the
+ * paper's `initialize`). On success *out owns every device buffer and must be destroyed with
+ * cube_destroy. Errors: CUBE_E_INVALID (sizes), CUBE_E_NOMEM, CUBE_E_DEVICE. */
+int cube_create(const cube_params* params, void* stream, const cube_allocator* alloc, cube_sim** out);
+
+/* Release every resource of the simulation (the paper's `finalize`). NULL is a no-op. */
+void cube_destroy(cube_sim* sim);
+
+/* Text of the last error of `sim` ("" if none). Owned by the simulation. */
+const char* cube_last_error(const cube_sim* sim);
+
+/* Zel'dovich initial conditions at a_init (Sec. 2.3.2, Fig. ic): Philox white noise on the
+ * np_side^3 lattice, FFT, BBKS amplitude, spectral displacement with Nyquist planes removed,
+ * then the two particle passes (count, then encode in cell order). Resets the schedule. */
+int cube_init_ic(cube_sim* sim);
+
+/* Replace the particles by n host particles: x (n,3) positions in fine cells, v (n,3) momenta,
+ * both FP64 row-major. Positions are encoded with Eq. (chi) in FP64, velocities rounded to
+ * FP32 and encoded with Eq. (nu) against the statistics of their cell; storage order is the
+ * input order, stably sorted by cell. Resets the schedule. Errors: CUBE_E_CAPACITY. */
+int cube_load_particles(cube_sim* sim, const double* x, const double* v, int64_t n);
+
+/* Advance k leapfrog steps (Fig. code): before the first step the initial half drift; each step
+ * deposits, solves, kicks and drifts; the last step ends with the final half drift at a_final.
+ * Returns CUBE_DONE when a_final has been reached (remaining steps are not taken).
+ * Errors: CUBE_E_CFL, CUBE_E_NONFINITE, CUBE_E_OVERFLOW, CUBE_E_STATE. */
+int cube_step(cube_sim* sim, int32_t k);
+
+/* Scale factor of the particle positions (a_init before the first step, a_final at the end). */
+double cube_scale_factor(const cube_sim* sim);
+/* Number of steps completed. */
+int32_t cube_steps_done(const cube_sim* sim);
+/* Current particle count. */
+int64_t cube_num_particles(const cube_sim* sim);
+
+/* CIC density contrast delta = rho/<rho> - 1 of the current state (Sec. 3), nm^3 FP32 values
+ * x-fastest, into `dst` (host memory if dst_on_device == 0, else device memory). */
+int cube_get_density(cube_sim* sim, float* dst, int dst_on_device);
+
+/* Auto power spectrum of the current state, Eq. (cps): CIC density, FFT, shells |n| rounded to
+ * the nearest integer for n = 1 .. nbins (nbins <= nm_side/2). Host outputs of length nbins:
+ * mean |k| (h/Mpc), mean P ((Mpc/h)^3, FP64 shell sums) and the number of modes. */
+int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* nmodes);
+
+/* Checkpoint, the paper's "disjoint state" {rho_c, v_c, chi, nu} (Sec. 2.3.1): host buffers.
+ * cnt: nc^3 uint32; chi: 3 planes of n codes (uint8 chi+128 for x_bytes 1, uint16 chi+32768
+ * for 2); nu: 3 planes of n codes (int8 or int16); vc: 3 planes of nc^3 FP32; vs: nc^3 FP32
+ * decode scales sigma sqrt(2/pi) of Eq. (v). cube_get_state writes them (n = current count);
+ * cube_set_state reads them and also sets the scale factor and completed-step count. */
+typedef struct {
+  uint32_t* cnt;
+  void* chi;
+  void* nu;
+  float* vc;
+  float* vs;
+  int64_t n;
+  double a;
+  int32_t steps_done;
+} cube_state_view;
+int cube_get_state(cube_sim* sim, cube_state_view* out);
+int cube_set_state(cube_sim* sim, const cube_state_view* in);
+
+/* ---- stages of one step, for parity checks and profiling -------------------------------- */
+
+/* CIC deposit of the current state into the mesh: delta in FP32 (exact integer accumulation,
+ * one rounding). */
+int cube_stage_deposit(cube_sim* sim);
+/* Poisson solve in place on the mesh: phi = IFFT( -3/2 Omega_m / |k|^2 FFT(delta) ). */
+int cube_stage_solve(cube_sim* sim);
+/* Kick + drift + re-encode + counting sort with the potential held in the mesh:
+ * v += kfac * D (D the unnormalised 4-point gradient, so kfac = -K/12), x += dfac * v. */
+int cube_stage_move(cube_sim* sim, float kfac, float dfac);
+/* Copy the real-space mesh (nm^3 FP32, x fastest) to or from host memory. */
+int cube_get_mesh(cube_sim* sim, float* host_dst);
+int cube_set_mesh(cube_sim* sim, const float* host_src);
+/* Zel'dovich displacement (3 planes of np^3 FP32, fine cells, lattice order) of the last
+ * cube_init_ic, computed again from the noise. */
+int cube_get_ic_displacement(cube_sim* sim, float* host_dst);
+/* FP32 decode table T[nu] = tan(pi nu / M) and FP32 edge table of Eq. (nu), host copies;
+ * sizes M and M - 1 with M = 2^(8 v_bytes) - 1. */
+int cube_get_tables(cube_sim* sim, float* decode, float* edges);
+
+/* Per-step kick and drift factors of the schedule (host, FP64): drift0, then kick[j], drift[j]
+ * for j = 0 .. n_steps-1. kick/drift must have n_steps entries. */
+int cube_get_schedule(const cube_sim* sim, double* drift0, double* kick, double* drift);
+
+/* Device memory held by the simulation, in bytes. */
+int64_t cube_device_bytes(const cube_sim* sim);
+
+/* Time of each kernel class of the last cube_step call measured with HIP events on the
+ * simulation's stream (milliseconds, summed over the steps of that call): index 0 deposit,
+ * 1 FFT + Green's function, 2 move count pass, 3 link + scan, 4 move scatter pass. Requires
+ * profiling enabled with cube_set_profiling(sim, 1). */
+int cube_set_profiling(cube_sim* sim, int enable);
+int cube_get_timings(const cube_sim* sim, double* ms5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CUBE_H */

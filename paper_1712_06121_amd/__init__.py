@@ -1,0 +1,12 @@
+"""MI355X-native hot path of CUBE's information-optimised particle-mesh step (arXiv:1712.06121).
+
+The product is libcube.so (HIP kernels for gfx950 behind the C ABI in include/cube.h); this
+package holds its sources (csrc/), the in-tree build (build.py) and the ctypes binding
+(binding.py). Importing the package does not load the library; ``Sim`` does, and fails loudly
+when the library has not been built.
+"""
+from .binding import (CUBE_DONE, CUBE_OK, EXPORTED, LIB_PATH, SIGMA_GLOBAL, SIGMA_PER_CELL, CubeError, Sim,
+                      load_library)
+
+__all__ = ["Sim", "CubeError", "load_library", "LIB_PATH", "EXPORTED", "SIGMA_GLOBAL", "SIGMA_PER_CELL", "CUBE_OK",
+           "CUBE_DONE"]

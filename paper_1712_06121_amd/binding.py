@@ -1,0 +1,289 @@
+"""ctypes binding of libcube (include/cube.h): argument marshalling only.
+
+Every step of the particle-mesh path runs in the HIP kernels of libcube.so; this module only
+converts numpy arrays and parameters, supplies PyTorch's stream and (optionally) PyTorch's
+caching allocator for device memory, and raises ``CubeError`` for non-zero status codes.
+The library must have been built in-tree (``python -m paper_1712_06121_amd.build``); there is no
+fallback of any kind when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_int64,
+                    c_size_t, c_uint64, c_void_p)
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libcube.so")
+
+CUBE_OK, CUBE_DONE = 0, 1
+ERRORS = {-1: "CUBE_E_INVALID", -2: "CUBE_E_NOMEM", -3: "CUBE_E_DEVICE", -4: "CUBE_E_CAPACITY", -5: "CUBE_E_CFL",
+          -6: "CUBE_E_NONFINITE", -7: "CUBE_E_OVERFLOW", -8: "CUBE_E_STATE"}
+SIGMA_GLOBAL, SIGMA_PER_CELL = 0, 1
+
+EXPORTED = [
+    "cube_create", "cube_destroy", "cube_last_error", "cube_init_ic", "cube_load_particles", "cube_step",
+    "cube_scale_factor", "cube_steps_done", "cube_num_particles", "cube_get_density", "cube_get_power",
+    "cube_get_state", "cube_set_state", "cube_stage_deposit", "cube_stage_solve", "cube_stage_move",
+    "cube_get_mesh", "cube_set_mesh", "cube_get_ic_displacement", "cube_get_tables", "cube_get_schedule",
+    "cube_device_bytes", "cube_set_profiling", "cube_get_timings",
+]
+
+
+class CubeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CubeParams(Structure):
+    _fields_ = [("np_side", c_int32), ("nm_side", c_int32), ("nc_side", c_int32), ("x_bytes", c_int32),
+                ("v_bytes", c_int32), ("sigma_mode", c_int32), ("n_steps", c_int32), ("spacing", c_int32),
+                ("box", c_double), ("omega_m", c_double), ("omega_l", c_double), ("h", c_double),
+                ("sigma8", c_double), ("n_s", c_double), ("a_init", c_double), ("a_final", c_double),
+                ("seed", c_uint64), ("capacity", c_int64)]
+
+
+ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class CubeAllocator(Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", c_void_p)]
+
+
+class CubeStateView(Structure):
+    _fields_ = [("cnt", c_void_p), ("chi", c_void_p), ("nu", c_void_p), ("vc", c_void_p), ("vs", c_void_p),
+                ("n", c_int64), ("a", c_double), ("steps_done", c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libcube.so; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcube.so not found at {path}: build it with `python -m paper_1712_06121_amd.build`")
+    lib = ctypes.CDLL(path)
+    sim_p = c_void_p
+    lib.cube_create.argtypes = [POINTER(CubeParams), c_void_p, POINTER(CubeAllocator), POINTER(c_void_p)]
+    lib.cube_destroy.argtypes = [sim_p]
+    lib.cube_destroy.restype = None
+    lib.cube_last_error.argtypes = [sim_p]
+    lib.cube_last_error.restype = c_char_p
+    for name in ("cube_init_ic", "cube_stage_deposit", "cube_stage_solve"):
+        getattr(lib, name).argtypes = [sim_p]
+    lib.cube_load_particles.argtypes = [sim_p, c_void_p, c_void_p, c_int64]
+    lib.cube_step.argtypes = [sim_p, c_int32]
+    lib.cube_scale_factor.argtypes = [sim_p]
+    lib.cube_scale_factor.restype = c_double
+    lib.cube_steps_done.argtypes = [sim_p]
+    lib.cube_steps_done.restype = c_int32
+    lib.cube_num_particles.argtypes = [sim_p]
+    lib.cube_num_particles.restype = c_int64
+    lib.cube_get_density.argtypes = [sim_p, c_void_p, c_int]
+    lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.cube_get_state.argtypes = [sim_p, POINTER(CubeStateView)]
+    lib.cube_set_state.argtypes = [sim_p, POINTER(CubeStateView)]
+    lib.cube_stage_move.argtypes = [sim_p, c_float, c_float]
+    lib.cube_get_mesh.argtypes = [sim_p, c_void_p]
+    lib.cube_set_mesh.argtypes = [sim_p, c_void_p]
+    lib.cube_get_ic_displacement.argtypes = [sim_p, c_void_p]
+    lib.cube_get_tables.argtypes = [sim_p, c_void_p, c_void_p]
+    lib.cube_get_schedule.argtypes = [sim_p, c_void_p, c_void_p, c_void_p]
+    lib.cube_device_bytes.argtypes = [sim_p]
+    lib.cube_device_bytes.restype = c_int64
+    lib.cube_set_profiling.argtypes = [sim_p, c_int]
+    lib.cube_get_timings.argtypes = [sim_p, c_void_p]
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> c_void_p:
+    return c_void_p(a.ctypes.data)
+
+
+class Sim:
+    """One simulation box. Parameters as in ``cube_params`` (include/cube.h)."""
+
+    def __init__(self, np_side: int, nm_side: int, box: float, nc_side: int | None = None, x_bytes: int = 1,
+                 v_bytes: int = 1, sigma_mode: int = SIGMA_PER_CELL, omega_m: float = 0.3, omega_l: float | None = None,
+                 h: float = 0.7, sigma8: float = 0.8, n_s: float = 1.0, a_init: float = 0.02, a_final: float = 1.0,
+                 n_steps: int = 50, spacing: int = 0, seed: int = 1, capacity: int = 0, torch_memory: bool = True,
+                 **_ignored):
+        self._lib = load_library()
+        self.np_side, self.nm, self.nc = np_side, nm_side, nc_side or nm_side // 4
+        self.x_bytes, self.v_bytes, self.n_steps = x_bytes, v_bytes, n_steps
+        self.box = box
+        self.params = CubeParams(np_side, nm_side, self.nc, x_bytes, v_bytes, sigma_mode, n_steps, spacing, box,
+                                 omega_m, 1.0 - omega_m if omega_l is None else omega_l, h, sigma8, n_s, a_init,
+                                 a_final, seed, capacity)
+        self._keep = []
+        stream = c_void_p(0)
+        alloc_p = None
+        try:
+            import torch
+            if torch.cuda.is_available():
+                stream = c_void_p(torch.cuda.current_stream().cuda_stream)
+                if torch_memory:
+                    dev = torch.cuda.current_device()
+                    tstream = torch.cuda.current_stream()
+
+                    def _alloc(nbytes, _user):
+                        try:
+                            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, tstream)
+                        except Exception:  # out of memory: the library reports CUBE_E_NOMEM
+                            return None
+
+                    def _free(ptr, _user):
+                        torch.cuda.caching_allocator_delete(ptr)
+
+                    a = CubeAllocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+                    self._keep.append(a)
+                    alloc_p = byref(a)
+        except ImportError:
+            pass
+        self._stream = stream
+        self._h = c_void_p()
+        rc = self._lib.cube_create(byref(self.params), stream, alloc_p, byref(self._h))
+        if rc != CUBE_OK:
+            raise CubeError(rc, "cube_create failed")
+
+    # ---- helpers -----------------------------------------------------------------------------
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise CubeError(rc, self._lib.cube_last_error(self._h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.cube_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def chi_dtype(self):
+        return np.uint8 if self.x_bytes == 1 else np.uint16
+
+    @property
+    def nu_dtype(self):
+        return np.int8 if self.v_bytes == 1 else np.int16
+
+    # ---- calls -------------------------------------------------------------------------------
+    def init_ic(self):
+        self._check(self._lib.cube_init_ic(self._h))
+
+    def load_particles(self, x, v):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert x.shape == v.shape and x.ndim == 2 and x.shape[1] == 3
+        self._check(self._lib.cube_load_particles(self._h, _ptr(x), _ptr(v), x.shape[0]))
+
+    def step(self, k: int = 1) -> int:
+        return self._check(self._lib.cube_step(self._h, k))
+
+    @property
+    def a(self) -> float:
+        return self._lib.cube_scale_factor(self._h)
+
+    @property
+    def steps_done(self) -> int:
+        return self._lib.cube_steps_done(self._h)
+
+    @property
+    def n(self) -> int:
+        return self._lib.cube_num_particles(self._h)
+
+    def get_density(self) -> np.ndarray:
+        out = np.empty((self.nm,) * 3, dtype=np.float32)
+        self._check(self._lib.cube_get_density(self._h, _ptr(out), 0))
+        return out
+
+    def get_power(self, nbins: int | None = None):
+        nb = nbins or self.nm // 2
+        k, pk, nm = (np.empty(nb) for _ in range(3))
+        self._check(self._lib.cube_get_power(self._h, nb, _ptr(k), _ptr(pk), _ptr(nm)))
+        return k, pk, nm
+
+    def get_state(self) -> dict:
+        n = self.n
+        nc3 = self.nc**3
+        st = dict(cnt=np.empty(nc3, np.uint32), chi=np.empty((3, n), self.chi_dtype), nu=np.empty((3, n), self.nu_dtype),
+                  vc=np.empty((3, nc3), np.float32), vs=np.empty(nc3, np.float32))
+        view = CubeStateView(_ptr(st["cnt"]), _ptr(st["chi"]), _ptr(st["nu"]), _ptr(st["vc"]), _ptr(st["vs"]), n, 0.0, 0)
+        self._check(self._lib.cube_get_state(self._h, byref(view)))
+        st["a"] = view.a
+        st["steps_done"] = view.steps_done
+        return st
+
+    def set_state(self, cnt, chi, nu, vc, vs, steps_done: int = 0):
+        cnt = np.ascontiguousarray(cnt, np.uint32)
+        chi = np.ascontiguousarray(chi, self.chi_dtype)
+        nu = np.ascontiguousarray(nu, self.nu_dtype)
+        vc = np.ascontiguousarray(vc, np.float32)
+        vs = np.ascontiguousarray(vs, np.float32)
+        view = CubeStateView(_ptr(cnt), _ptr(chi), _ptr(nu), _ptr(vc), _ptr(vs), chi.shape[1], 0.0, steps_done)
+        self._check(self._lib.cube_set_state(self._h, byref(view)))
+
+    def stage_deposit(self):
+        self._check(self._lib.cube_stage_deposit(self._h))
+
+    def stage_solve(self):
+        self._check(self._lib.cube_stage_solve(self._h))
+
+    def stage_move(self, kfac: float, dfac: float):
+        self._check(self._lib.cube_stage_move(self._h, c_float(kfac), c_float(dfac)))
+
+    def get_mesh(self) -> np.ndarray:
+        out = np.empty((self.nm,) * 3, dtype=np.float32)
+        self._check(self._lib.cube_get_mesh(self._h, _ptr(out)))
+        return out
+
+    def set_mesh(self, field):
+        f = np.ascontiguousarray(field, dtype=np.float32)
+        assert f.shape == (self.nm,) * 3
+        self._check(self._lib.cube_set_mesh(self._h, _ptr(f)))
+
+    def get_ic_displacement(self) -> np.ndarray:
+        out = np.empty((3,) + (self.np_side,) * 3, dtype=np.float32)
+        self._check(self._lib.cube_get_ic_displacement(self._h, _ptr(out)))
+        return out
+
+    def get_tables(self):
+        m = (1 << (8 * self.v_bytes)) - 1
+        dec, edg = np.empty(m, np.float32), np.empty(m - 1, np.float32)
+        self._check(self._lib.cube_get_tables(self._h, _ptr(dec), _ptr(edg)))
+        return dec, edg
+
+    def get_schedule(self):
+        d0 = c_double()
+        k, d = np.empty(self.n_steps), np.empty(self.n_steps)
+        self._check(self._lib.cube_get_schedule(self._h, byref(d0), _ptr(k), _ptr(d)))
+        return d0.value, k, d
+
+    @property
+    def device_bytes(self) -> int:
+        return self._lib.cube_device_bytes(self._h)
+
+    def set_profiling(self, on: bool = True):
+        self._check(self._lib.cube_set_profiling(self._h, int(on)))
+
+    def get_timings(self) -> np.ndarray:
+        out = np.empty(5)
+        self._check(self._lib.cube_get_timings(self._h, _ptr(out)))
+        return out

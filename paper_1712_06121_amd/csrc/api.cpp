@@ -1,0 +1,589 @@
+// C ABI of libcube (declared in include/cube.h): simulation lifetime, schedule, and the calls of
+// the paper's main program (Fig. code): initial conditions, steps, checkpoint I/O, analysis.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "cube_internal.h"
+
+struct cube_sim {
+  cube::Sim s;
+};
+
+namespace cube {
+
+void* Sim::dmalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (has_alloc) {
+    p = alloc.alloc(bytes, alloc.user);
+    if (!p) throw Error{CUBE_E_NOMEM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes"};
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{CUBE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+  }
+  dev_bytes += (int64_t)bytes;
+  owned.push_back(p);
+  sizes.push_back(bytes);
+  return p;
+}
+
+void Sim::dfree(void* p) {
+  if (!p) return;
+  for (size_t i = 0; i < owned.size(); ++i) {
+    if (owned[i] == p) {
+      dev_bytes -= (int64_t)sizes[i];
+      owned.erase(owned.begin() + i);
+      sizes.erase(sizes.begin() + i);
+      break;
+    }
+  }
+  if (has_alloc) alloc.free(p, alloc.user);
+  else (void)hipFree(p);
+}
+
+namespace {
+
+bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+void build_tables(Sim& s) {
+  const int m = (1 << (8 * s.nnu)) - 1;
+  const int half = (m - 1) / 2;
+  s.vm = m;
+  s.h_tdec.resize(m);
+  s.h_tedge.resize(m - 1);
+  for (int nu = -half; nu <= half; ++nu) s.h_tdec[nu + half] = (float)std::tan(M_PI * (double)nu / (double)m);
+  for (int j = -(half - 1); j <= half; ++j) {
+    const double e = std::tan(M_PI * ((double)j - 0.5) / (double)m);
+    float f = (float)e;
+    if ((double)f < e) f = std::nextafterf(f, INFINITY);
+    s.h_tedge[j + half - 1] = f;
+  }
+  s.tdec = static_cast<float*>(s.dmalloc(sizeof(float) * m));
+  s.tedge = static_cast<float*>(s.dmalloc(sizeof(float) * (m - 1)));
+  CUBE_HIP(hipMemcpy(s.tdec, s.h_tdec.data(), sizeof(float) * m, hipMemcpyHostToDevice));
+  CUBE_HIP(hipMemcpy(s.tedge, s.h_tedge.data(), sizeof(float) * (m - 1), hipMemcpyHostToDevice));
+}
+
+void build_schedule(Sim& s) {
+  const int n = s.p.n_steps;
+  s.a_int.resize(n + 1);
+  for (int j = 0; j <= n; ++j) {
+    if (s.p.spacing == 0)
+      s.a_int[j] = s.p.a_init * std::pow(s.p.a_final / s.p.a_init, (double)j / n);
+    else
+      s.a_int[j] = s.p.a_init + (s.p.a_final - s.p.a_init) * (double)j / n;
+  }
+  s.a_int[0] = s.p.a_init;
+  s.a_int[n] = s.p.a_final;
+  s.a_half.resize(n);
+  for (int j = 0; j < n; ++j) s.a_half[j] = std::sqrt(s.a_int[j] * s.a_int[j + 1]);
+  s.drift0 = s.cosmo.drift(s.a_int[0], s.a_half[0]);
+  s.kicks.resize(n);
+  s.drifts.resize(n);
+  for (int j = 0; j < n; ++j) s.kicks[j] = s.cosmo.kick(s.a_int[j], s.a_int[j + 1]);
+  for (int j = 0; j + 1 < n; ++j) s.drifts[j] = s.cosmo.drift(s.a_half[j], s.a_half[j + 1]);
+  s.drifts[n - 1] = s.cosmo.drift(s.a_half[n - 1], s.a_int[n]);
+}
+
+void reset_schedule(Sim& s) {
+  s.steps_done = 0;
+  s.half_drift_done = false;
+}
+
+void check_flags(Sim& s) {
+  uint32_t f = 0;
+  CUBE_HIP(hipMemcpyAsync(&f, s.flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s.stream));
+  CUBE_HIP(hipStreamSynchronize(s.stream));
+  if (!f) return;
+  CUBE_HIP(hipMemsetAsync(s.flags, 0, sizeof(uint32_t), s.stream));
+  CUBE_HIP(hipStreamSynchronize(s.stream));
+  if (f & FLAG_NONFINITE) throw Error{CUBE_E_NONFINITE, "non-finite particle position or velocity"};
+  if (f & FLAG_CFL) throw Error{CUBE_E_CFL, "a particle moved more than one coarse cell in one step"};
+  if (f & FLAG_OVERFLOW) throw Error{CUBE_E_OVERFLOW, "velocity outside the range of the moment accumulators"};
+  if (f & FLAG_COUNT) throw Error{CUBE_E_STATE, "particle count changed during the move"};
+}
+
+void copy_mesh_out(Sim& s, float* dst, hipMemcpyKind kind) {
+  const size_t pitch = s.mesh_plan.row_floats() * sizeof(float);
+  CUBE_HIP(hipMemcpy2DAsync(dst, sizeof(float) * s.nm, s.mesh, pitch, sizeof(float) * s.nm, (size_t)s.nm * s.nm, kind,
+                            s.stream));
+  CUBE_HIP(hipStreamSynchronize(s.stream));
+}
+
+float gconst(const Sim& s) {
+  const double n3 = (double)s.nm * s.nm * s.nm;
+  return (float)(-1.5 * s.p.omega_m / n3);
+}
+
+void require_particles(const Sim& s) {
+  if (!s.have_particles) throw Error{CUBE_E_STATE, "no particles: call cube_init_ic, cube_load_particles or cube_set_state"};
+}
+
+// psi buffers for the initial conditions; returns the transformed noise buffer
+void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps) {
+  const size_t fbytes = s.lat_plan.field_floats() * sizeof(float);
+  float* wk = nullptr;
+  if (s.lat_plan.n == s.mesh_plan.n) {
+    wk = s.mesh;
+  } else {
+    wk = static_cast<float*>(s.dmalloc(fbytes));
+    temps.push_back(wk);
+  }
+  for (int d = 0; d < 3; ++d) {
+    psi[d] = static_cast<float*>(s.dmalloc(fbytes));
+    temps.push_back(psi[d]);
+  }
+  launch_noise(s.lat_plan, wk, s.p.seed, s.stream);
+  fft_forward_3d(s.lat_plan, wk, s.stream);
+  // i n_d tab[|n|^2] gives the displacement in fine cells after the unnormalised inverse FFT
+  const int h = s.np / 2;
+  const int64_t ntab = 3LL * h * h + 1;
+  std::vector<float> tab(ntab, 0.0f);
+  const double box = s.p.box, np3 = (double)s.np * s.np * s.np;
+  const double ai = s.p.a_init;
+  for (int64_t n2 = 1; n2 < ntab; ++n2) {
+    const double k = 2.0 * M_PI * std::sqrt((double)n2) / box;
+    const double amp = std::sqrt(np3 * s.cosmo.pk(k, ai) / (box * box * box));
+    tab[n2] = (float)(amp * (double)s.nm / (2.0 * M_PI * (double)n2 * np3));
+  }
+  float* dtab = static_cast<float*>(s.dmalloc(sizeof(float) * ntab));
+  temps.push_back(dtab);
+  CUBE_HIP(hipMemcpy(dtab, tab.data(), sizeof(float) * ntab, hipMemcpyHostToDevice));
+  for (int d = 0; d < 3; ++d) fft_ic_component(s.lat_plan, wk, psi[d], dtab, d, s.stream);
+  *wk_out = wk;
+}
+
+int fail(cube_sim* sim, const Error& e) {
+  if (sim) sim->s.last_error = e.msg;
+  return e.code;
+}
+
+#define CUBE_GUARD(sim, ...)                                                          \
+  try {                                                                               \
+    __VA_ARGS__;                                                                      \
+  } catch (const ::cube::Error& e) {                                                  \
+    return ::cube::fail(sim, e);                                                      \
+  } catch (const std::bad_alloc&) {                                                   \
+    return ::cube::fail(sim, ::cube::Error{CUBE_E_NOMEM, "host allocation failed"});  \
+  } catch (const std::exception& e) {                                                 \
+    return ::cube::fail(sim, ::cube::Error{CUBE_E_INVALID, e.what()});                \
+  }
+
+}  // namespace
+}  // namespace cube
+
+using cube::Error;
+
+extern "C" {
+
+int cube_create(const cube_params* params, void* stream, const cube_allocator* alloc, cube_sim** out) {
+  if (!params || !out) return CUBE_E_INVALID;
+  *out = nullptr;
+  cube_sim* sim = nullptr;
+  try {
+    sim = new cube_sim();
+  } catch (...) {
+    return CUBE_E_NOMEM;
+  }
+  cube::Sim& s = sim->s;
+  try {
+    s.p = *params;
+    s.stream = static_cast<hipStream_t>(stream);
+    if (alloc && alloc->alloc && alloc->free) {
+      s.alloc = *alloc;
+      s.has_alloc = true;
+    }
+    const cube_params& p = s.p;
+    if (!cube::pow2(p.nm_side) || p.nm_side < 32 || p.nm_side > 2048)
+      throw Error{CUBE_E_INVALID, "nm_side must be a power of two in [32, 2048]"};
+    if (p.nc_side * 4 != p.nm_side) throw Error{CUBE_E_INVALID, "nc_side must be nm_side / 4"};
+    if (p.nc_side % 4 != 0) throw Error{CUBE_E_INVALID, "nc_side must be a multiple of 4"};
+    if (!cube::pow2(p.np_side) || p.np_side < 32 || p.np_side > 2048 || p.np_side % p.nc_side != 0)
+      throw Error{CUBE_E_INVALID, "np_side must be a power of two in [32, 2048] and a multiple of nc_side"};
+    if (p.x_bytes < 1 || p.x_bytes > 2 || p.v_bytes < 1 || p.v_bytes > 2)
+      throw Error{CUBE_E_INVALID, "x_bytes and v_bytes must be 1 or 2"};
+    if (p.sigma_mode != CUBE_SIGMA_GLOBAL && p.sigma_mode != CUBE_SIGMA_PER_CELL)
+      throw Error{CUBE_E_INVALID, "sigma_mode must be CUBE_SIGMA_GLOBAL or CUBE_SIGMA_PER_CELL"};
+    if (p.n_steps < 1 || !(p.a_init > 0.0) || !(p.a_final > p.a_init) || !(p.box > 0.0) || !(p.omega_m > 0.0))
+      throw Error{CUBE_E_INVALID, "need n_steps >= 1, 0 < a_init < a_final, box > 0, omega_m > 0"};
+    s.nm = p.nm_side;
+    s.nc = p.nc_side;
+    s.np = p.np_side;
+    s.nchi = p.x_bytes;
+    s.nnu = p.v_bytes;
+    s.nc3 = (int64_t)s.nc * s.nc * s.nc;
+    s.capacity = p.capacity > 0 ? p.capacity : (int64_t)s.np * s.np * s.np;
+    if (s.capacity >= (int64_t)1 << 40) throw Error{CUBE_E_INVALID, "capacity too large"};
+    s.cosmo.om = p.omega_m;
+    s.cosmo.ol = p.omega_l;
+    s.cosmo.h = p.h;
+    s.cosmo.sigma8 = p.sigma8;
+    s.cosmo.ns = p.n_s;
+    s.cosmo.init();
+    cube::build_schedule(s);
+    // particle state, double buffered
+    for (int b = 0; b < 2; ++b) {
+      const size_t pb = (size_t)3 * s.capacity * (s.nchi + s.nnu);
+      char* buf = static_cast<char*>(s.dmalloc(pb));
+      s.chi[b] = buf;
+      s.nu[b] = buf + (size_t)3 * s.capacity * s.nchi;
+      s.pbytes = pb;
+      s.cnt[b] = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * s.nc3));
+      s.off[b] = static_cast<uint64_t*>(s.dmalloc(sizeof(uint64_t) * (s.nc3 + 1)));
+      s.vc[b] = static_cast<float*>(s.dmalloc(sizeof(float) * 3 * s.nc3));
+      s.vs[b] = static_cast<float*>(s.dmalloc(sizeof(float) * s.nc3));
+    }
+    s.vinv = static_cast<float*>(s.dmalloc(sizeof(float) * s.nc3));
+    s.mig = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * 27 * s.nc3));
+    s.slot = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * 27 * s.nc3));
+    s.mom = static_cast<int64_t*>(s.dmalloc(sizeof(int64_t) * 4 * s.nc3));
+    s.dev = static_cast<double*>(s.dmalloc(sizeof(double) * s.nc3));
+    s.nblk = (s.nc3 + 255) / 256;
+    s.blk_n = static_cast<uint64_t*>(s.dmalloc(sizeof(uint64_t) * s.nblk));
+    s.blk_q = static_cast<int64_t*>(s.dmalloc(sizeof(int64_t) * s.nblk));
+    s.blk_off = static_cast<uint64_t*>(s.dmalloc(sizeof(uint64_t) * s.nblk));
+    s.scal = static_cast<double*>(s.dmalloc(sizeof(double) * 8));
+    s.flags = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * 4));
+    s.pk_acc = static_cast<double*>(s.dmalloc(sizeof(double) * 3 * (s.nm / 2 + 1)));
+    cube::fft_plan_create(s, s.mesh_plan, s.nm);
+    if (s.np == s.nm) s.lat_plan = s.mesh_plan;
+    else cube::fft_plan_create(s, s.lat_plan, s.np);
+    s.mesh = static_cast<float*>(s.dmalloc(s.mesh_plan.field_floats() * sizeof(float)));
+    cube::build_tables(s);
+    CUBE_HIP(hipMemsetAsync(s.mom, 0, sizeof(int64_t) * 4 * s.nc3, s.stream));
+    CUBE_HIP(hipMemsetAsync(s.flags, 0, sizeof(uint32_t) * 4, s.stream));
+    CUBE_HIP(hipMemsetAsync(s.mesh, 0, s.mesh_plan.field_floats() * sizeof(float), s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+    for (auto& e : s.ev) CUBE_HIP(hipEventCreate(&e));
+    s.a_now = p.a_init;
+  } catch (const Error& e) {
+    const int code = e.code;
+    std::string msg = e.msg;
+    cube_destroy(sim);
+    (void)msg;
+    return code;
+  } catch (...) {
+    cube_destroy(sim);
+    return CUBE_E_NOMEM;
+  }
+  *out = sim;
+  return CUBE_OK;
+}
+
+void cube_destroy(cube_sim* sim) {
+  if (!sim) return;
+  cube::Sim& s = sim->s;
+  if (s.stream) (void)hipStreamSynchronize(s.stream);
+  else (void)hipDeviceSynchronize();
+  for (auto& e : s.ev)
+    if (e) (void)hipEventDestroy(e);
+  std::vector<void*> all = s.owned;
+  for (void* p : all) s.dfree(p);
+  delete sim;
+}
+
+const char* cube_last_error(const cube_sim* sim) { return sim ? sim->s.last_error.c_str() : "null simulation"; }
+
+int cube_init_ic(cube_sim* sim) {
+  if (!sim) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    std::vector<void*> temps;
+    float* psi[3];
+    float* wk = nullptr;
+    cube::ic_fields(s, psi, &wk, temps);
+    s.n = (int64_t)s.np * s.np * s.np;
+    if (s.n > s.capacity) throw Error{CUBE_E_CAPACITY, "np_side^3 exceeds the capacity"};
+    const double a = s.p.a_init;
+    const float vfac = (float)(a * a * s.cosmo.E(a) * s.cosmo.f(a));
+    cube::launch_move(s, 2, 0.0f, 0.0f, psi, vfac, s.stream, nullptr);
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+    for (void* t : temps) s.dfree(t);
+    s.have_particles = true;
+    cube::reset_schedule(s);
+    cube::check_flags(s);
+  });
+  return CUBE_OK;
+}
+
+int cube_get_ic_displacement(cube_sim* sim, float* host_dst) {
+  if (!sim || !host_dst) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    std::vector<void*> temps;
+    float* psi[3];
+    float* wk = nullptr;
+    cube::ic_fields(s, psi, &wk, temps);
+    const size_t pitch = s.lat_plan.row_floats() * sizeof(float);
+    const size_t np3 = (size_t)s.np * s.np * s.np;
+    for (int d = 0; d < 3; ++d)
+      CUBE_HIP(hipMemcpy2DAsync(host_dst + d * np3, sizeof(float) * s.np, psi[d], pitch, sizeof(float) * s.np,
+                                (size_t)s.np * s.np, hipMemcpyDeviceToHost, s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+    for (void* t : temps) s.dfree(t);
+  });
+  return CUBE_OK;
+}
+
+int cube_load_particles(cube_sim* sim, const double* x, const double* v, int64_t n) {
+  if (!sim || n < 0 || (n > 0 && (!x || !v))) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    if (n > s.capacity) throw Error{CUBE_E_CAPACITY, "particle count exceeds the capacity"};
+    if (n >= ((int64_t)1 << 32)) throw Error{CUBE_E_CAPACITY, "load path supports fewer than 2^32 particles"};
+    double* d = static_cast<double*>(s.dmalloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1)));
+    if (n > 0) {
+      CUBE_HIP(hipMemcpyAsync(d, x, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s.stream));
+      CUBE_HIP(hipMemcpyAsync(d + 3 * n, v, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s.stream));
+    }
+    s.n = n;
+    cube::launch_load(s, d, nullptr, n, s.stream);
+    s.dfree(d);
+    s.have_particles = true;
+    cube::reset_schedule(s);
+    cube::check_flags(s);
+  });
+  return CUBE_OK;
+}
+
+int cube_step(cube_sim* sim, int32_t k) {
+  if (!sim || k < 0) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  int rc = CUBE_OK;
+  CUBE_GUARD(sim, {
+    cube::require_particles(s);
+    if (s.profiling)
+      for (double& t : s.timings) t = 0.0;
+    for (int i = 0; i < k; ++i) {
+      if (s.steps_done >= s.p.n_steps) {
+        rc = CUBE_DONE;
+        break;
+      }
+      if (!s.half_drift_done) {
+        cube::launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+        s.half_drift_done = true;
+      }
+      const int j = s.steps_done;
+      hipEvent_t* ev = s.profiling ? s.ev : nullptr;
+      if (ev) CUBE_HIP(hipEventRecord(ev[0], s.stream));
+      cube::launch_deposit(s, s.stream);
+      if (ev) CUBE_HIP(hipEventRecord(ev[1], s.stream));
+      cube::fft_solve_poisson(s.mesh_plan, s.mesh, cube::gconst(s), s.stream);
+      if (ev) CUBE_HIP(hipEventRecord(ev[2], s.stream));
+      cube::launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream,
+                        ev ? ev + 3 : nullptr);
+      if (ev) {
+        CUBE_HIP(hipEventRecord(ev[5], s.stream));
+        CUBE_HIP(hipEventSynchronize(ev[5]));
+        float ms[5];
+        CUBE_HIP(hipEventElapsedTime(&ms[0], ev[0], ev[1]));
+        CUBE_HIP(hipEventElapsedTime(&ms[1], ev[1], ev[2]));
+        CUBE_HIP(hipEventElapsedTime(&ms[2], ev[2], ev[3]));
+        CUBE_HIP(hipEventElapsedTime(&ms[3], ev[3], ev[4]));
+        CUBE_HIP(hipEventElapsedTime(&ms[4], ev[4], ev[5]));
+        for (int q = 0; q < 5; ++q) s.timings[q] += ms[q];
+      }
+      s.steps_done++;
+    }
+    cube::check_flags(s);
+    if (s.steps_done >= s.p.n_steps && rc == CUBE_OK && k > 0) rc = CUBE_OK;
+  });
+  return rc;
+}
+
+double cube_scale_factor(const cube_sim* sim) {
+  if (!sim) return 0.0;
+  const cube::Sim& s = sim->s;
+  if (s.steps_done >= s.p.n_steps) return s.p.a_final;
+  if (s.steps_done == 0) return s.p.a_init;
+  return s.a_half[s.steps_done];
+}
+
+int32_t cube_steps_done(const cube_sim* sim) { return sim ? sim->s.steps_done : 0; }
+int64_t cube_num_particles(const cube_sim* sim) { return sim ? sim->s.n : 0; }
+
+int cube_stage_deposit(cube_sim* sim) {
+  if (!sim) return CUBE_E_INVALID;
+  CUBE_GUARD(sim, {
+    cube::require_particles(sim->s);
+    cube::launch_deposit(sim->s, sim->s.stream);
+    CUBE_HIP(hipStreamSynchronize(sim->s.stream));
+  });
+  return CUBE_OK;
+}
+
+int cube_stage_solve(cube_sim* sim) {
+  if (!sim) return CUBE_E_INVALID;
+  CUBE_GUARD(sim, {
+    cube::fft_solve_poisson(sim->s.mesh_plan, sim->s.mesh, cube::gconst(sim->s), sim->s.stream);
+    CUBE_HIP(hipStreamSynchronize(sim->s.stream));
+  });
+  return CUBE_OK;
+}
+
+int cube_stage_move(cube_sim* sim, float kfac, float dfac) {
+  if (!sim) return CUBE_E_INVALID;
+  CUBE_GUARD(sim, {
+    cube::require_particles(sim->s);
+    cube::launch_move(sim->s, 0, kfac, dfac, nullptr, 0.0f, sim->s.stream, nullptr);
+    CUBE_HIP(hipStreamSynchronize(sim->s.stream));
+    cube::check_flags(sim->s);
+  });
+  return CUBE_OK;
+}
+
+int cube_get_mesh(cube_sim* sim, float* host_dst) {
+  if (!sim || !host_dst) return CUBE_E_INVALID;
+  CUBE_GUARD(sim, { cube::copy_mesh_out(sim->s, host_dst, hipMemcpyDeviceToHost); });
+  return CUBE_OK;
+}
+
+int cube_set_mesh(cube_sim* sim, const float* host_src) {
+  if (!sim || !host_src) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    const size_t pitch = s.mesh_plan.row_floats() * sizeof(float);
+    CUBE_HIP(hipMemcpy2DAsync(s.mesh, pitch, host_src, sizeof(float) * s.nm, sizeof(float) * s.nm, (size_t)s.nm * s.nm,
+                              hipMemcpyHostToDevice, s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+  });
+  return CUBE_OK;
+}
+
+int cube_get_density(cube_sim* sim, float* dst, int dst_on_device) {
+  if (!sim || !dst) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    cube::require_particles(s);
+    cube::launch_deposit(s, s.stream);
+    cube::copy_mesh_out(s, dst, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  });
+  return CUBE_OK;
+}
+
+int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* nmodes) {
+  if (!sim || !k || !pk || !nmodes) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  if (nbins < 1 || nbins > s.nm / 2) return cube::fail(sim, Error{CUBE_E_INVALID, "nbins must be in [1, nm/2]"});
+  CUBE_GUARD(sim, {
+    cube::require_particles(s);
+    const int nb = s.nm / 2 + 1;
+    cube::launch_deposit(s, s.stream);
+    CUBE_HIP(hipMemsetAsync(s.pk_acc, 0, sizeof(double) * 3 * nb, s.stream));
+    cube::fft_power(s.mesh_plan, s.mesh, s.pk_acc, s.stream);
+    std::vector<double> acc(3 * nb);
+    CUBE_HIP(hipMemcpyAsync(acc.data(), s.pk_acc, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+    const double L = s.p.box, kf = 2.0 * M_PI / L;
+    const double nm6 = std::pow((double)s.nm, 6);
+    for (int b = 1; b <= nbins; ++b) {
+      const double w = acc[2 * nb + b];
+      nmodes[b - 1] = w;
+      k[b - 1] = w > 0 ? kf * acc[nb + b] / w : 0.0;
+      pk[b - 1] = w > 0 ? (L * L * L / nm6) * acc[b] / w : 0.0;
+    }
+  });
+  return CUBE_OK;
+}
+
+int cube_get_state(cube_sim* sim, cube_state_view* out) {
+  if (!sim || !out || !out->cnt || !out->chi || !out->nu || !out->vc || !out->vs) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    cube::require_particles(s);
+    const int c = s.cur;
+    const hipStream_t st = s.stream;
+    CUBE_HIP(hipMemcpyAsync(out->cnt, s.cnt[c], sizeof(uint32_t) * s.nc3, hipMemcpyDeviceToHost, st));
+    for (int d = 0; d < 3; ++d) {
+      CUBE_HIP(hipMemcpyAsync(static_cast<char*>(out->chi) + (size_t)d * s.n * s.nchi,
+                              static_cast<char*>(s.chi[c]) + (size_t)d * s.capacity * s.nchi, (size_t)s.n * s.nchi,
+                              hipMemcpyDeviceToHost, st));
+      CUBE_HIP(hipMemcpyAsync(static_cast<char*>(out->nu) + (size_t)d * s.n * s.nnu,
+                              static_cast<char*>(s.nu[c]) + (size_t)d * s.capacity * s.nnu, (size_t)s.n * s.nnu,
+                              hipMemcpyDeviceToHost, st));
+    }
+    CUBE_HIP(hipMemcpyAsync(out->vc, s.vc[c], sizeof(float) * 3 * s.nc3, hipMemcpyDeviceToHost, st));
+    CUBE_HIP(hipMemcpyAsync(out->vs, s.vs[c], sizeof(float) * s.nc3, hipMemcpyDeviceToHost, st));
+    CUBE_HIP(hipStreamSynchronize(st));
+    out->n = s.n;
+    out->a = cube_scale_factor(sim);
+    out->steps_done = s.steps_done;
+  });
+  return CUBE_OK;
+}
+
+int cube_set_state(cube_sim* sim, const cube_state_view* in) {
+  if (!sim || !in || !in->cnt || !in->chi || !in->nu || !in->vc || !in->vs || in->n < 0) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    if (in->n > s.capacity) throw Error{CUBE_E_CAPACITY, "particle count exceeds the capacity"};
+    std::vector<uint64_t> off(s.nc3 + 1);
+    uint64_t run = 0;
+    for (int64_t c = 0; c < s.nc3; ++c) {
+      off[c] = run;
+      run += in->cnt[c];
+    }
+    off[s.nc3] = run;
+    if ((int64_t)run != in->n) throw Error{CUBE_E_INVALID, "sum of cell counts differs from n"};
+    const int c = s.cur;
+    const hipStream_t st = s.stream;
+    s.n = in->n;
+    CUBE_HIP(hipMemcpyAsync(s.cnt[c], in->cnt, sizeof(uint32_t) * s.nc3, hipMemcpyHostToDevice, st));
+    CUBE_HIP(hipMemcpyAsync(s.off[c], off.data(), sizeof(uint64_t) * (s.nc3 + 1), hipMemcpyHostToDevice, st));
+    for (int d = 0; d < 3; ++d) {
+      CUBE_HIP(hipMemcpyAsync(static_cast<char*>(s.chi[c]) + (size_t)d * s.capacity * s.nchi,
+                              static_cast<const char*>(in->chi) + (size_t)d * s.n * s.nchi, (size_t)s.n * s.nchi,
+                              hipMemcpyHostToDevice, st));
+      CUBE_HIP(hipMemcpyAsync(static_cast<char*>(s.nu[c]) + (size_t)d * s.capacity * s.nnu,
+                              static_cast<const char*>(in->nu) + (size_t)d * s.n * s.nnu, (size_t)s.n * s.nnu,
+                              hipMemcpyHostToDevice, st));
+    }
+    CUBE_HIP(hipMemcpyAsync(s.vc[c], in->vc, sizeof(float) * 3 * s.nc3, hipMemcpyHostToDevice, st));
+    CUBE_HIP(hipMemcpyAsync(s.vs[c], in->vs, sizeof(float) * s.nc3, hipMemcpyHostToDevice, st));
+    CUBE_HIP(hipStreamSynchronize(st));
+    s.have_particles = true;
+    s.steps_done = in->steps_done < 0 ? 0 : (in->steps_done > s.p.n_steps ? s.p.n_steps : in->steps_done);
+    s.half_drift_done = s.steps_done > 0;
+  });
+  return CUBE_OK;
+}
+
+int cube_get_tables(cube_sim* sim, float* decode, float* edges) {
+  if (!sim || !decode || !edges) return CUBE_E_INVALID;
+  const cube::Sim& s = sim->s;
+  std::memcpy(decode, s.h_tdec.data(), sizeof(float) * s.h_tdec.size());
+  std::memcpy(edges, s.h_tedge.data(), sizeof(float) * s.h_tedge.size());
+  return CUBE_OK;
+}
+
+int cube_get_schedule(const cube_sim* sim, double* drift0, double* kick, double* drift) {
+  if (!sim || !drift0 || !kick || !drift) return CUBE_E_INVALID;
+  const cube::Sim& s = sim->s;
+  *drift0 = s.drift0;
+  for (int j = 0; j < s.p.n_steps; ++j) {
+    kick[j] = s.kicks[j];
+    drift[j] = s.drifts[j];
+  }
+  return CUBE_OK;
+}
+
+int64_t cube_device_bytes(const cube_sim* sim) { return sim ? sim->s.dev_bytes : 0; }
+
+int cube_set_profiling(cube_sim* sim, int enable) {
+  if (!sim) return CUBE_E_INVALID;
+  sim->s.profiling = enable != 0;
+  return CUBE_OK;
+}
+
+int cube_get_timings(const cube_sim* sim, double* ms5) {
+  if (!sim || !ms5) return CUBE_E_INVALID;
+  for (int i = 0; i < 5; ++i) ms5[i] = sim->s.timings[i];
+  return CUBE_OK;
+}
+
+}  // extern "C"

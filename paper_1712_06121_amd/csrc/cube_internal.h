@@ -1,0 +1,152 @@
+// Internal structures of libcube (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cube.h"
+
+namespace cube {
+
+// ---- error handling -------------------------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define CUBE_HIP(call)                                                                       \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::cube::Error{CUBE_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// device-side error flags (bit set by kernels, checked on the host after a step)
+enum : uint32_t {
+  FLAG_CFL = 1u,        // |displacement| > one coarse cell
+  FLAG_NONFINITE = 2u,  // NaN/Inf position or velocity
+  FLAG_OVERFLOW = 4u,   // moment accumulator out of range
+  FLAG_COUNT = 8u,      // total count after the move differs from N
+};
+
+// ---- FFT plan: one cubic size N, half-complex padded layout --------------------------------
+// Real-space field: N x N rows of `pitch_c * 2` floats (x fastest, N used). Fourier space:
+// the same rows hold pitch_c complex values, x-frequencies 0..N/2 (Nyquist at index N/2);
+// columns beyond N/2 are padding processed as don't-care values.
+struct FFTPlan {
+  int n = 0;
+  int bx = 0;        // column block width of the y/z passes (complex values)
+  int pitch_c = 0;   // complex values per row, = n/2 + bx
+  float2* tw = nullptr;    // exp(-2 pi i t / n), t = 0..n-1 (device)
+  float* k2 = nullptr;     // (2 pi f(t) / n)^2 with f the signed frequency of index t (device)
+  size_t field_floats() const { return (size_t)n * n * pitch_c * 2; }
+  size_t row_floats() const { return (size_t)pitch_c * 2; }
+};
+
+// ---- host cosmology (FP64) -----------------------------------------------------------------
+struct Cosmo {
+  double om, ol, ok, h, sigma8, ns;
+  double d_norm = 1.0, amp = 1.0;
+  double E(double a) const;
+  double growth_unnorm(double a) const;
+  double D(double a) const { return growth_unnorm(a) / d_norm; }
+  double f(double a) const;
+  double kick(double a0, double a1) const;
+  double drift(double a0, double a1) const;
+  double transfer(double k) const;
+  double pk(double k, double a) const;  // linear P(k) at a, (Mpc/h)^3
+  void init();
+};
+
+// ---- simulation ------------------------------------------------------------------------------
+struct Sim {
+  cube_params p{};
+  hipStream_t stream = nullptr;
+  cube_allocator alloc{};
+  bool has_alloc = false;
+  std::string last_error;
+
+  int nm = 0, nc = 0, np = 0, nchi = 1, nnu = 1;
+  int64_t nc3 = 0, capacity = 0, n = 0;
+  int64_t dev_bytes = 0;
+
+  // particle state, double buffered: [cur] is current
+  void* chi[2] = {nullptr, nullptr};   // 3 planes x capacity x nchi bytes
+  void* nu[2] = {nullptr, nullptr};    // 3 planes x capacity x nnu bytes
+  uint32_t* cnt[2] = {nullptr, nullptr};
+  uint64_t* off[2] = {nullptr, nullptr};  // nc3 + 1 (exclusive prefix, last = N)
+  float* vc[2] = {nullptr, nullptr};      // 3 x nc3
+  float* vs[2] = {nullptr, nullptr};      // nc3 decode scale
+  int cur = 0;
+
+  // move scratch
+  float* vinv = nullptr;       // nc3 encode scale 1/(sigma sqrt(2/pi))
+  uint32_t* mig = nullptr;     // 27 x nc3 counts per (source cell, displacement)
+  uint32_t* slot = nullptr;    // 27 x nc3 prefix per (new cell, source offset)
+  int64_t* mom = nullptr;      // 4 x nc3: S1x, S1y, S1z, S2
+  double* dev = nullptr;       // nc3 3-D velocity variance per cell
+  uint64_t* blk_n = nullptr;   // per link block: count
+  int64_t* blk_q = nullptr;    // per link block: dispersion sum
+  uint64_t* blk_off = nullptr; // per link block: exclusive prefix
+  double* scal = nullptr;      // [0] sigma_g^2
+  uint32_t* flags = nullptr;   // error flags
+  int64_t nblk = 0;
+
+  // mesh
+  FFTPlan mesh_plan;
+  float* mesh = nullptr;
+  FFTPlan lat_plan;            // lattice FFT for initial conditions (size np)
+
+  // codec tables (device)
+  float* tdec = nullptr;   // M entries
+  float* tedge = nullptr;  // M - 1 entries
+  std::vector<float> h_tdec, h_tedge;
+  int vm = 255;
+
+  // power spectrum accumulators
+  double* pk_acc = nullptr;  // 3 x (nm/2 + 1)
+
+  // schedule
+  Cosmo cosmo{};
+  std::vector<double> a_int, a_half, kicks, drifts;
+  double drift0 = 0.0;
+  int steps_done = 0;
+  bool half_drift_done = false;
+  double a_now = 0.0;
+  bool have_particles = false;
+
+  // profiling
+  bool profiling = false;
+  hipEvent_t ev[12] = {};
+  double timings[5] = {0, 0, 0, 0, 0};
+
+  size_t pbytes = 0;  // bytes of one particle-state buffer (chi and nu planes)
+
+  void* dmalloc(size_t bytes);
+  void dfree(void* p);
+  std::vector<void*> owned;
+  std::vector<size_t> sizes;
+};
+
+// ---- launchers (implemented in the .hip files) ---------------------------------------------
+void fft_plan_create(Sim& s, FFTPlan& pl, int n);
+void fft_plan_destroy(Sim& s, FFTPlan& pl);
+void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st);
+void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st);
+void fft_power(const FFTPlan& pl, float* data, double* acc, hipStream_t st);
+// initial conditions: psi_d = IFFT( i n_d tab[|n|^2] W ) with W the transformed noise
+void fft_ic_component(const FFTPlan& pl, const float* wk, float* out, const float* tab, int dim,
+                      hipStream_t st);
+
+void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st);
+void launch_deposit(Sim& s, hipStream_t st);
+// move: mode 0 = step (force from mesh), 1 = drift only (no force), 2 = initial conditions
+void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
+                 hipEvent_t* evs);
+void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream_t st);
+void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmodes);
+
+}  // namespace cube

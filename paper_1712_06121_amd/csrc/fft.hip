@@ -1,0 +1,454 @@
+// Three-dimensional real FFT for the Poisson solve, the power spectrum and the initial
+// conditions, written for gfx950 (64-wide wavefronts, 160 KB LDS per CU).
+//
+// The paper solves the mesh force "in Fourier space" with FFTW (Sec. 1, Sec. 2.3.3); here the
+// transform is a hand-written Stockham autosort FFT held in LDS:
+//   x pass : rows along x are contiguous; each workgroup loads a few rows, does a complex FFT
+//            of length N/2 on the even/odd-packed row and untangles the real spectrum
+//            (frequencies 0..N/2, the Nyquist value at index N/2 of the padded row).
+//   y pass : a workgroup loads a block of BX adjacent x-frequency columns for all N rows
+//            (BX*8-byte coalesced segments) and transforms them along y.
+//   z pass : the same column kernel along z. For the Poisson solve the forward z transform,
+//            the Green's function -3/2 Omega_m / |k|^2 (and the 1/N^3 normalisation) and the
+//            inverse z transform are fused into one pass, so the solve costs five passes over
+//            the mesh: x, y, z+G+z^-1, y^-1, x^-1.
+// All passes work in place on one buffer of N x N rows of pitch_c complex values.
+#include "cube_internal.h"
+
+namespace cube {
+namespace {
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+constexpr int first_radix(int l) { return (ilog2c(l) % 3 == 1) ? 2 : ((ilog2c(l) % 3 == 2) ? 4 : 8); }
+
+__device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+// multiply by exp(DIR i pi / 2): DIR = -1 gives -i a, DIR = +1 gives i a
+template <int DIR>
+__device__ __forceinline__ float2 mul_pi2(float2 a) {
+  return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+template <int DIR>
+__device__ __forceinline__ float2 twid(const float2* __restrict__ tw, int idx) {
+  float2 w = tw[idx];
+  if (DIR > 0) w.y = -w.y;
+  return w;
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v);
+
+template <>
+__device__ __forceinline__ void dft<2, -1>(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+template <>
+__device__ __forceinline__ void dft<2, 1>(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = a + b;
+  v[1] = a - b;
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  float2 t0 = v0 + v2, t1 = v0 - v2, t2 = v1 + v3, t3 = mul_pi2<DIR>(v1 - v3);
+  v0 = t0 + t2;
+  v2 = t0 - t2;
+  v1 = t1 + t3;
+  v3 = t1 - t3;
+}
+template <>
+__device__ __forceinline__ void dft<4, -1>(float2* v) { dft4<-1>(v[0], v[1], v[2], v[3]); }
+template <>
+__device__ __forceinline__ void dft<4, 1>(float2* v) { dft4<1>(v[0], v[1], v[2], v[3]); }
+
+template <int DIR>
+__device__ __forceinline__ void dft8(float2* v) {
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  const float c = 0.70710678118654752440f;
+  const float d = (float)DIR;
+  float2 w1 = make_float2(c * (o1.x - d * o1.y), c * (o1.y + d * o1.x));
+  float2 w2 = mul_pi2<DIR>(o2);
+  float2 w3 = make_float2(-c * (o3.x + d * o3.y), c * (d * o3.x - o3.y));
+  v[0] = e0 + o0;
+  v[4] = e0 - o0;
+  v[1] = e1 + w1;
+  v[5] = e1 - w1;
+  v[2] = e2 + w2;
+  v[6] = e2 - w2;
+  v[3] = e3 + w3;
+  v[7] = e3 - w3;
+}
+template <>
+__device__ __forceinline__ void dft<8, -1>(float2* v) { dft8<-1>(v); }
+template <>
+__device__ __forceinline__ void dft<8, 1>(float2* v) { dft8<1>(v); }
+
+// One radix-R Stockham stage over NL lines of length L held in LDS. Element t of line l sits at
+// lds[l * LS + t * TS]. Twiddles come from a table of exp(-2 pi i t / (L * TWS)).
+template <int L, int R, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS>
+__device__ __forceinline__ void stockham_stage(float2* lds, const float2* __restrict__ tw) {
+  constexpr int NBF = L / R;
+  constexpr int NB = NL * NBF;
+  constexpr int PER = (NB + BLOCK - 1) / BLOCK;
+  float2 v[PER][R];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int i = threadIdx.x + p * BLOCK;
+    if (NB % BLOCK == 0 || i < NB) {
+      const int l = (TS == 1) ? i / NBF : i % NL;
+      const int j = (TS == 1) ? i % NBF : i / NL;
+      const float2* base = lds + l * LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[p][r] = base[(j + r * NBF) * TS];
+      if (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], twid<DIR>(tw, r * k * (L / (NS * R)) * TWS));
+      }
+      dft<R, DIR>(v[p]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int i = threadIdx.x + p * BLOCK;
+    if (NB % BLOCK == 0 || i < NB) {
+      const int l = (TS == 1) ? i / NBF : i % NL;
+      const int j = (TS == 1) ? i % NBF : i / NL;
+      const int k = j % NS;
+      const int dst = (j / NS) * NS * R + k;
+      float2* base = lds + l * LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[(dst + r * NS) * TS] = v[p][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS>
+__device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw) {
+  if constexpr (NS < L) {
+    constexpr int R = (NS == 1) ? first_radix(L) : 8;
+    stockham_stage<L, R, NS, NL, LS, TS, BLOCK, DIR, TWS>(lds, tw);
+    fft_lds<L, NS * R, NL, LS, TS, BLOCK, DIR, TWS>(lds, tw);
+  }
+}
+
+// ---- x pass: real rows <-> half spectrum ---------------------------------------------------
+template <int N>
+struct RowCfg {
+  static constexpr int H = N / 2;
+  static constexpr int NL = (2048 / H) < 1 ? 1 : 2048 / H;
+  static constexpr int BLOCK = 256;
+};
+
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int64_t pitch_f,
+                                                  const float2* __restrict__ tw) {
+  constexpr int H = RowCfg<N>::H, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
+  __shared__ float2 lds[NL * H];
+  const int64_t row0 = (int64_t)blockIdx.x * NL;
+  constexpr int F4 = N / 4;
+  for (int i = threadIdx.x; i < NL * F4; i += BLOCK) {
+    const int l = i / F4, c = i % F4;
+    const float4 q = *reinterpret_cast<const float4*>(data + (row0 + l) * pitch_f + 4 * c);
+    lds[l * H + 2 * c] = make_float2(q.x, q.y);
+    lds[l * H + 2 * c + 1] = make_float2(q.z, q.w);
+  }
+  __syncthreads();
+  fft_lds<H, 1, NL, H, 1, BLOCK, -1, 2>(lds, tw);
+  constexpr int NP = H / 2 + 1;
+  for (int i = threadIdx.x; i < NL * NP; i += BLOCK) {
+    const int l = i / NP, k = i % NP;
+    const float2 zk = lds[l * H + k];
+    const float2 zm = conjf2(lds[l * H + ((H - k) & (H - 1))]);
+    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+    const float2 dd = zk - zm;
+    const float2 o = make_float2(0.5f * dd.y, -0.5f * dd.x);
+    const float2 wo = cmul(tw[k], o);
+    float2* out = reinterpret_cast<float2*>(data + (row0 + l) * pitch_f);
+    out[k] = e + wo;
+    if (k != H - k) out[H - k] = conjf2(e - wo);
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int64_t pitch_f,
+                                                  const float2* __restrict__ tw) {
+  constexpr int H = N / 2, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
+  constexpr int LS = H + 1;
+  __shared__ float2 lds[NL * LS];
+  const int64_t row0 = (int64_t)blockIdx.x * NL;
+  for (int i = threadIdx.x; i < NL * LS; i += BLOCK) {
+    const int l = i / LS, c = i % LS;
+    lds[l * LS + c] = reinterpret_cast<const float2*>(data + (row0 + l) * pitch_f)[c];
+  }
+  __syncthreads();
+  constexpr int NP = H / 2 + 1;
+  for (int i = threadIdx.x; i < NL * NP; i += BLOCK) {
+    const int l = i / NP, k = i % NP;
+    const float2 xk = lds[l * LS + k];
+    const float2 xm = conjf2(lds[l * LS + H - k]);
+    const float2 a = xk + xm;
+    const float2 b = cmul(conjf2(tw[k]), xk - xm);
+    lds[l * LS + k] = make_float2(a.x - b.y, a.y + b.x);
+    if (k != 0 && k != H - k) lds[l * LS + H - k] = make_float2(a.x + b.y, -a.y + b.x);
+  }
+  __syncthreads();
+  fft_lds<H, 1, NL, LS, 1, BLOCK, 1, 2>(lds, tw);
+  constexpr int F4 = N / 4;
+  for (int i = threadIdx.x; i < NL * F4; i += BLOCK) {
+    const int l = i / F4, c = i % F4;
+    const float2 a = lds[l * LS + 2 * c], b = lds[l * LS + 2 * c + 1];
+    *reinterpret_cast<float4*>(data + (row0 + l) * pitch_f + 4 * c) = make_float4(a.x, a.y, b.x, b.y);
+  }
+}
+
+// ---- y / z passes: blocks of BX columns ------------------------------------------------------
+template <int N>
+struct ColCfg {
+  static constexpr int BX = (N >= 2048) ? 8 : ((N >= 1024) ? 8 : 16);
+  static constexpr int BLOCK = (N >= 2048) ? 512 : 256;
+};
+
+enum ColMode { COL_FWD = 0, COL_INV = 1, COL_GREEN = 2, COL_POWER = 3, COL_PSI = 4 };
+
+struct ColArgs {
+  const float* k2;   // squared angular wavenumber per index
+  float gconst;      // Green's constant (includes 1/N^3)
+  double* acc;       // power accumulators (3 x (N/2 + 1))
+  const float* tab;  // initial-condition factor per |n|^2
+  int dim;           // initial-condition component
+  int half;          // N / 2
+};
+
+__device__ __forceinline__ int signed_freq(int t, int n) { return t <= n / 2 ? t : t - n; }
+
+template <int N, int MODE>
+__global__ __launch_bounds__(ColCfg<N>::BLOCK) void k_fft_col(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                             int64_t tstride, int64_t ostride,
+                                                             const float2* __restrict__ tw, ColArgs a) {
+  constexpr int BX = ColCfg<N>::BX, BLOCK = ColCfg<N>::BLOCK;
+  __shared__ float2 lds[N * BX];
+  const int cb = blockIdx.x, o = blockIdx.y;
+  const int64_t base = (int64_t)o * ostride + (int64_t)cb * BX;
+  constexpr int Q = BX / 2;
+  for (int i = threadIdx.x; i < N * Q; i += BLOCK) {
+    const int t = i / Q, c = i % Q;
+    const float4 q = *reinterpret_cast<const float4*>(src + base + (int64_t)t * tstride + 2 * c);
+    lds[t * BX + 2 * c] = make_float2(q.x, q.y);
+    lds[t * BX + 2 * c + 1] = make_float2(q.z, q.w);
+  }
+  __syncthreads();
+  if constexpr (MODE == COL_FWD || MODE == COL_GREEN || MODE == COL_POWER)
+    fft_lds<N, 1, BX, 1, BX, BLOCK, -1, 1>(lds, tw);
+  if constexpr (MODE == COL_GREEN) {
+    // z pass: t = z frequency index, column x_c = cb*BX + b, o = y index
+    const float ky2 = a.k2[o];
+    for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
+      const int t = i / BX, b = i % BX;
+      const int xc = cb * BX + b;
+      const float kk = a.k2[xc] + ky2 + a.k2[t];
+      const float g = (xc == 0 && o == 0 && t == 0) ? 0.0f : a.gconst / kk;
+      const float2 v = lds[i];
+      lds[i] = make_float2(v.x * g, v.y * g);
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == COL_PSI) {
+    const int fy = signed_freq(o, N);
+    for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
+      const int t = i / BX, b = i % BX;
+      const int xc = cb * BX + b;
+      const int fz = signed_freq(t, N);
+      const int n2 = xc * xc + fy * fy + fz * fz;
+      const bool nyq = (xc >= a.half) || (fy == a.half) || (fz == a.half) || (fy == -a.half) || (fz == -a.half);
+      const int nd = a.dim == 0 ? xc : (a.dim == 1 ? fy : fz);
+      const float f = (nyq || n2 == 0) ? 0.0f : a.tab[n2] * (float)nd;
+      const float2 v = lds[i];
+      lds[i] = make_float2(-v.y * f, v.x * f);
+    }
+    __syncthreads();
+  }
+  if constexpr (MODE == COL_POWER) {
+    // shell sums of |delta_k|^2; only real frequencies 0..N/2 along x
+    constexpr int NB = N / 2 + 1;
+    __shared__ double acc[3 * NB];
+    for (int i = threadIdx.x; i < 3 * NB; i += BLOCK) acc[i] = 0.0;
+    __syncthreads();
+    const int fy = signed_freq(o, N);
+    for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
+      const int t = i / BX, b = i % BX;
+      const int xc = cb * BX + b;
+      if (xc > a.half) continue;
+      const int fz = signed_freq(t, N);
+      const int n2 = xc * xc + fy * fy + fz * fz;
+      if (n2 == 0) continue;
+      int m = (int)sqrtf((float)n2);
+      while ((2 * m + 1) * (2 * m + 1) <= 4 * n2) ++m;
+      while (m > 0 && (2 * m - 1) * (2 * m - 1) > 4 * n2) --m;
+      if (m < 1 || m > a.half) continue;
+      const double w = (xc == 0 || xc == a.half) ? 1.0 : 2.0;
+      const float2 v = lds[i];
+      const double p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      atomicAdd(&acc[m], w * p);
+      atomicAdd(&acc[NB + m], w * sqrt((double)n2));
+      atomicAdd(&acc[2 * NB + m], w);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 3 * NB; i += BLOCK) {
+      const double v = acc[i];
+      if (v != 0.0) atomicAdd(&a.acc[i], v);
+    }
+    return;
+  }
+  if constexpr (MODE == COL_INV || MODE == COL_GREEN || MODE == COL_PSI)
+    fft_lds<N, 1, BX, 1, BX, BLOCK, 1, 1>(lds, tw);
+  for (int i = threadIdx.x; i < N * Q; i += BLOCK) {
+    const int t = i / Q, c = i % Q;
+    const float2 u = lds[t * BX + 2 * c], w = lds[t * BX + 2 * c + 1];
+    *reinterpret_cast<float4*>(dst + base + (int64_t)t * tstride + 2 * c) = make_float4(u.x, u.y, w.x, w.y);
+  }
+}
+
+// ---- host dispatch ---------------------------------------------------------------------------
+template <int N>
+void run_x(const FFTPlan& pl, float* data, bool forward, hipStream_t st) {
+  const int64_t rows = (int64_t)N * N;
+  const dim3 grid((unsigned)(rows / RowCfg<N>::NL));
+  if (forward)
+    k_fft_x_r2c<N><<<grid, RowCfg<N>::BLOCK, 0, st>>>(data, (int64_t)pl.row_floats(), pl.tw);
+  else
+    k_fft_x_c2r<N><<<grid, RowCfg<N>::BLOCK, 0, st>>>(data, (int64_t)pl.row_floats(), pl.tw);
+  CUBE_HIP(hipGetLastError());
+}
+
+template <int N, int MODE>
+void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
+  const int ncb = (N / 2) / ColCfg<N>::BX + 1;
+  const int64_t pc = pl.pitch_c;
+  const int64_t tstride = axis == 1 ? pc : (int64_t)N * pc;
+  const int64_t ostride = axis == 1 ? (int64_t)N * pc : pc;
+  const dim3 grid(ncb, N);
+  k_fft_col<N, MODE><<<grid, ColCfg<N>::BLOCK, 0, st>>>(reinterpret_cast<const float2*>(src),
+                                                        reinterpret_cast<float2*>(dst), tstride, ostride, pl.tw, a);
+  CUBE_HIP(hipGetLastError());
+}
+
+template <int N>
+void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st) {
+  ColArgs a{pl.k2, gconst, nullptr, nullptr, 0, N / 2};
+  run_x<N>(pl, d, true, st);
+  run_col<N, COL_FWD>(pl, d, d, 1, a, st);
+  run_col<N, COL_GREEN>(pl, d, d, 2, a, st);
+  run_col<N, COL_INV>(pl, d, d, 1, a, st);
+  run_x<N>(pl, d, false, st);
+}
+
+template <int N>
+void forward_n(const FFTPlan& pl, float* d, hipStream_t st) {
+  ColArgs a{pl.k2, 0.f, nullptr, nullptr, 0, N / 2};
+  run_x<N>(pl, d, true, st);
+  run_col<N, COL_FWD>(pl, d, d, 1, a, st);
+  run_col<N, COL_FWD>(pl, d, d, 2, a, st);
+}
+
+template <int N>
+void power_n(const FFTPlan& pl, float* d, double* acc, hipStream_t st) {
+  ColArgs a{pl.k2, 0.f, acc, nullptr, 0, N / 2};
+  run_x<N>(pl, d, true, st);
+  run_col<N, COL_FWD>(pl, d, d, 1, a, st);
+  run_col<N, COL_POWER>(pl, d, d, 2, a, st);
+}
+
+template <int N>
+void ic_n(const FFTPlan& pl, const float* wk, float* out, const float* tab, int dim, hipStream_t st) {
+  ColArgs a{pl.k2, 0.f, nullptr, tab, dim, N / 2};
+  run_col<N, COL_PSI>(pl, wk, out, 2, a, st);
+  run_col<N, COL_INV>(pl, out, out, 1, a, st);
+  run_x<N>(pl, out, false, st);
+}
+
+#define CUBE_FFT_DISPATCH(n, CALL)                        \
+  switch (n) {                                            \
+    case 32: CALL(32); break;                             \
+    case 64: CALL(64); break;                             \
+    case 128: CALL(128); break;                           \
+    case 256: CALL(256); break;                           \
+    case 512: CALL(512); break;                           \
+    case 1024: CALL(1024); break;                         \
+    case 2048: CALL(2048); break;                         \
+    default: throw Error{CUBE_E_INVALID, "unsupported FFT size"}; \
+  }
+
+template <int N>
+constexpr int col_bx() { return ColCfg<N>::BX; }
+
+}  // namespace
+
+void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
+  pl.n = n;
+#define CUBE_BX(N) pl.bx = col_bx<N>()
+  CUBE_FFT_DISPATCH(n, CUBE_BX)
+#undef CUBE_BX
+  pl.pitch_c = n / 2 + pl.bx;
+  std::vector<float2> tw(n);
+  std::vector<float> k2(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int t = 0; t < n; ++t) {
+    const double ang = -two_pi * (double)t / (double)n;
+    tw[t] = make_float2((float)cos(ang), (float)sin(ang));
+    const int f = t <= n / 2 ? t : t - n;
+    const double k = two_pi * (double)f / (double)n;
+    k2[t] = (float)(k * k);
+  }
+  pl.tw = static_cast<float2*>(s.dmalloc(sizeof(float2) * n));
+  pl.k2 = static_cast<float*>(s.dmalloc(sizeof(float) * n));
+  CUBE_HIP(hipMemcpy(pl.tw, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
+  CUBE_HIP(hipMemcpy(pl.k2, k2.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+}
+
+void fft_plan_destroy(Sim& s, FFTPlan& pl) {
+  s.dfree(pl.tw);
+  s.dfree(pl.k2);
+  pl.tw = nullptr;
+  pl.k2 = nullptr;
+}
+
+void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st) {
+#define CUBE_CALL(N) solve_n<N>(pl, data, gconst, st)
+  CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
+#undef CUBE_CALL
+}
+
+void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st) {
+#define CUBE_CALL(N) forward_n<N>(pl, data, st)
+  CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
+#undef CUBE_CALL
+}
+
+void fft_power(const FFTPlan& pl, float* data, double* acc, hipStream_t st) {
+#define CUBE_CALL(N) power_n<N>(pl, data, acc, st)
+  CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
+#undef CUBE_CALL
+}
+
+void fft_ic_component(const FFTPlan& pl, const float* wk, float* out, const float* tab, int dim, hipStream_t st) {
+#define CUBE_CALL(N) ic_n<N>(pl, wk, out, tab, dim, st)
+  CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
+#undef CUBE_CALL
+}
+
+}  // namespace cube

@@ -1,0 +1,952 @@
+// Particle kernels of the compressed PM step for gfx950: integer CIC deposit, the two move passes
+// (count, then encode + scatter), the per-cell link/scan/statistics kernels, the initial-condition
+// lattice move and the load path.
+//
+// Storage (Sec. 2.1-2.2): particles are cell ordered; position codes chi (Eq. (chi)) and velocity
+// codes nu (Eq. (nu)) are structure-of-arrays byte planes; per coarse cell the count, the storage
+// offset, the mean velocity v_c and the decode scale sigma sqrt(2/pi) of Eq. (v).
+//
+// All kernels work on tiles of T^3 coarse cells (one workgroup per tile). Deposit gathers: the
+// workgroup that owns a tile of fine cells reads the particles of its tile and of the ring of
+// neighbouring coarse cells and accumulates exact integer CIC weights in LDS (no float atomics,
+// no global atomics), so the density is bit-reproducible. The move passes scatter: each particle
+// is handled by the workgroup that owns its coarse cell; the potential tile with a 3-cell halo
+// sits in LDS for the 4-point gradient.
+//
+// The arithmetic follows one fixed sequence of IEEE operations (no FMA contraction: this file is
+// compiled with -ffp-contract=off) so that the encoding, cell counts and order are reproducible
+// bit for bit from identical inputs.
+#include <cstring>
+#include <type_traits>
+
+#include <rocprim/rocprim.hpp>
+
+#include "cube_internal.h"
+
+namespace cube {
+namespace {
+
+constexpr int T = 4;            // coarse cells per tile side
+constexpr int TC = T * T * T;   // own cells per tile
+constexpr int F = 4 * T;        // fine cells per tile side
+constexpr int PH = F + 6;       // potential tile side (3-cell halo)
+constexpr int RG = T + 2;       // new-cell region side (tile + ring)
+constexpr int RC = RG * RG * RG;
+constexpr int SRC = RC;         // deposit source cells (tile + ring)
+constexpr int BLK = 256;
+constexpr int LINK_BLK = 256;
+
+template <int NCHI>
+using chi_t = std::conditional_t<NCHI == 1, uint8_t, uint16_t>;
+template <int NNU>
+using nu_t = std::conditional_t<NNU == 1, int8_t, int16_t>;
+
+__device__ __forceinline__ int wrapi(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+__device__ __forceinline__ void set_flag(uint32_t* flags, uint32_t f) { atomicOr(flags, f); }
+
+// exclusive prefix of up to 256 uint32 values held one per thread; returns the total
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* out, int n, uint32_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t x = (tid < n) ? v : 0u;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t wbase = 0, total = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) wbase += wsum[w];
+    total += wsum[w];
+  }
+  if (tid < n) out[tid] = wbase + inc - x;
+  if (tid == 0) out[n] = total;
+  __syncthreads();
+  return total;
+}
+
+__device__ __forceinline__ int find_cell(const uint32_t* pre, int ncell, uint32_t i) {
+  int lo = 0, hi = ncell;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+struct TileGeom {
+  int cx0, cy0, cz0;
+};
+__device__ __forceinline__ TileGeom tile_of(int b, int nt) {
+  TileGeom g;
+  g.cx0 = (b % nt) * T;
+  g.cy0 = ((b / nt) % nt) * T;
+  g.cz0 = (b / (nt * nt)) * T;
+  return g;
+}
+
+// ---------------------------------------------------------------------------------------------
+// CIC deposit (Sec. 3 "CIC"; cell centres at i + 1/2), exact integer weights, gather by tile.
+// ---------------------------------------------------------------------------------------------
+struct DepArgs {
+  const void* chi;
+  const uint32_t* cnt;
+  const uint64_t* off;
+  int64_t cap;
+  float* mesh;
+  int64_t pitch_f;
+  int nm, nc, nt;
+  double inv_mean;
+};
+
+template <int NCHI>
+__global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
+  using CT = chi_t<NCHI>;
+  constexpr int SH = 8 * NCHI - 1;
+  __shared__ unsigned long long rho[F * F * F];
+  __shared__ uint32_t pre[SRC + 1];
+  __shared__ uint64_t start[SRC];
+  __shared__ uint32_t wsum[BLK / 64];
+  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  for (int i = threadIdx.x; i < F * F * F; i += BLK) rho[i] = 0ull;
+  uint32_t cntv = 0;
+  if (threadIdx.x < SRC) {
+    const int s = threadIdx.x;
+    const int sx = s % RG - 1, sy = (s / RG) % RG - 1, sz = s / (RG * RG) - 1;
+    const int gx = wrapi(g.cx0 + sx, a.nc), gy = wrapi(g.cy0 + sy, a.nc), gz = wrapi(g.cz0 + sz, a.nc);
+    const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
+    cntv = a.cnt[c];
+    start[s] = a.off[c];
+  }
+  const uint32_t total = block_exclusive_scan(cntv, pre, SRC, wsum);
+  const CT* cx = static_cast<const CT*>(a.chi);
+  const CT* cy = cx + a.cap;
+  const CT* cz = cy + a.cap;
+  for (uint32_t i = threadIdx.x; i < total; i += BLK) {
+    const int s = find_cell(pre, SRC, i);
+    const int64_t p = (int64_t)start[s] + (i - pre[s]);
+    const int sl[3] = {s % RG - 1, (s / RG) % RG - 1, s / (RG * RG) - 1};
+    const int ch[3] = {(int)cx[p], (int)cy[p], (int)cz[p]};
+    int i0[3], w1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int pl = sl[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
+      i0[d] = pl >> SH;
+      w1[d] = pl & ((1 << SH) - 1);
+    }
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int z = i0[2] + dz;
+      if (z < 0 || z >= F) continue;
+      const unsigned long long wz = dz ? (unsigned long long)w1[2] : (unsigned long long)((1 << SH) - w1[2]);
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy) {
+        const int y = i0[1] + dy;
+        if (y < 0 || y >= F) continue;
+        const unsigned long long wy = dy ? (unsigned long long)w1[1] : (unsigned long long)((1 << SH) - w1[1]);
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int x = i0[0] + dx;
+          if (x < 0 || x >= F) continue;
+          const unsigned long long wx = dx ? (unsigned long long)w1[0] : (unsigned long long)((1 << SH) - w1[0]);
+          atomicAdd(&rho[(z * F + y) * F + x], wz * wy * wx);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int fx0 = g.cx0 * 4, fy0 = g.cy0 * 4, fz0 = g.cz0 * 4;
+  for (int i = threadIdx.x; i < F * F * F; i += BLK) {
+    const int x = i % F, y = (i / F) % F, z = i / (F * F);
+    const double r = (double)rho[i];
+    const float dlt = (float)(r * a.inv_mean - 1.0);
+    a.mesh[((int64_t)(fz0 + z) * a.nm + (fy0 + y)) * a.pitch_f + (fx0 + x)] = dlt;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Move passes. MODE 0: kick with the potential in the mesh + drift; MODE 1: drift only;
+// MODE 2: initial conditions (lattice + Zel'dovich displacement).
+// ---------------------------------------------------------------------------------------------
+struct MoveArgs {
+  const void* chi;
+  const void* nu;
+  const uint32_t* cnt;
+  const uint64_t* off;
+  const float* vc;
+  const float* vs;
+  void* chi_n;
+  void* nu_n;
+  const uint64_t* off_n;
+  const float* vc_n;
+  const float* vinv;
+  int64_t cap;
+  const float* mesh;
+  int64_t pitch_f;
+  int nm, nc, nt;
+  int64_t nc3;
+  float kf, df;
+  const float* tdec;
+  const float* tedge;
+  int vhalf;
+  uint32_t* mig;
+  const uint32_t* slot;
+  int64_t* mom;
+  uint32_t* flags;
+  // initial conditions
+  const float* psi0;
+  const float* psi1;
+  const float* psi2;
+  int64_t lat_pitch_f;
+  int np, q;
+  float vfac, lunit;
+};
+
+struct Moved {
+  float v[3];
+  int k[3];
+  int chi[3];
+  bool ok;
+};
+
+template <int NCHI, int NNU, int MODE>
+__device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* ph, int s, int64_t p, uint32_t li,
+                                               const TileGeom& g) {
+  using CT = chi_t<NCHI>;
+  using NT = nu_t<NNU>;
+  constexpr int SH = 8 * NCHI - 1;
+  const int o[3] = {s % T, (s / T) % T, s / (T * T)};
+  const int64_t c = (g.cx0 + o[0]) + (int64_t)a.nc * ((g.cy0 + o[1]) + (int64_t)a.nc * (g.cz0 + o[2]));
+  float l[3], v[3];
+  Moved m;
+  if constexpr (MODE == 2) {
+    const int lat[3] = {(int)(li % a.q), (int)((li / a.q) % a.q), (int)(li / (a.q * a.q))};
+    const int64_t gx = (int64_t)(g.cx0 + o[0]) * a.q + lat[0];
+    const int64_t gy = (int64_t)(g.cy0 + o[1]) * a.q + lat[1];
+    const int64_t gz = (int64_t)(g.cz0 + o[2]) * a.q + lat[2];
+    const int64_t pi = (gz * a.np + gy) * a.lat_pitch_f + gx;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float ps = (d == 0 ? a.psi0 : (d == 1 ? a.psi1 : a.psi2))[pi];
+      const float l0 = (float)(2 * lat[d] + 1) * a.lunit;
+      v[d] = a.vfac * ps;
+      l[d] = l0 + ps;
+    }
+  } else {
+    const CT* chi = static_cast<const CT*>(a.chi);
+    const NT* nu = static_cast<const NT*>(a.nu);
+    const float unit = (float)(1.0 / (double)(1 << SH));
+    int ch[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      ch[d] = (int)chi[d * a.cap + p];
+      l[d] = (float)(2 * ch[d] + 1) * unit;
+      int nuv = (int)nu[d * a.cap + p];
+      nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
+      v[d] = a.vc[d * a.nc3 + c] + a.vs[c] * a.tdec[nuv + a.vhalf];
+    }
+    if constexpr (MODE == 0) {
+      // CIC corners and weights (exact dyadic), potential tile coordinates offset by the halo
+      int i0[3];
+      float w0[3], w1[3];
+      const float wunit = (float)(1.0 / (double)(1 << SH));
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
+        i0[d] = (pl >> SH) + 3;
+        const int f = pl & ((1 << SH) - 1);
+        w0[d] = (float)((1 << SH) - f) * wunit;
+        w1[d] = (float)f * wunit;
+      }
+      const int sx = 1, sy = PH, sz = PH * PH;
+      const int strides[3] = {sx, sy, sz};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int e = strides[d];
+        float sacc[2];
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz) {
+          float racc[2];
+#pragma unroll
+          for (int cy = 0; cy < 2; ++cy) {
+            const int b0 = (i0[2] + cz) * sz + (i0[1] + cy) * sy + i0[0];
+            float dg[2];
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+              const int b = b0 + cx;
+              const float aa = ph[b + e] - ph[b - e];
+              const float bb = ph[b + 2 * e] - ph[b - 2 * e];
+              dg[cx] = 8.0f * aa - bb;
+            }
+            racc[cy] = w0[0] * dg[0] + w1[0] * dg[1];
+          }
+          sacc[cz] = w0[1] * racc[0] + w1[1] * racc[1];
+        }
+        const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
+        v[d] = v[d] + t * a.kf;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
+  }
+  m.ok = true;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float ln = l[d];
+    int k = 0;
+    float lw = ln;
+    if (!(ln == ln) || fabsf(ln) == INFINITY || !(v[d] == v[d]) || fabsf(v[d]) == INFINITY) {
+      set_flag(a.flags, FLAG_NONFINITE);
+      m.ok = false;
+      lw = 0.0f;
+    } else if (ln < -4.0f || ln >= 8.0f) {
+      set_flag(a.flags, FLAG_CFL);
+      m.ok = false;
+      lw = 0.0f;
+    } else if (ln < 0.0f) {
+      k = -1;
+      lw = ln + 4.0f;
+    } else if (ln >= 4.0f) {
+      k = 1;
+      lw = ln - 4.0f;
+    }
+    if (fabsf(v[d]) >= 32768.0f) {
+      set_flag(a.flags, FLAG_OVERFLOW);
+      m.ok = false;
+    }
+    int cq = (int)floorf(lw * (float)(1 << (SH - 1)));
+    cq = cq < 0 ? 0 : (cq > (1 << (SH + 1)) - 1 ? (1 << (SH + 1)) - 1 : cq);
+    m.k[d] = k;
+    m.chi[d] = cq;
+    m.v[d] = m.ok ? v[d] : 0.0f;
+  }
+  return m;
+}
+
+template <int NCHI, int MODE>
+__device__ __forceinline__ void load_potential(const MoveArgs& a, float* ph, const TileGeom& g) {
+  if constexpr (MODE == 0) {
+    const int fx0 = g.cx0 * 4 - 3, fy0 = g.cy0 * 4 - 3, fz0 = g.cz0 * 4 - 3;
+    for (int i = threadIdx.x; i < PH * PH * PH; i += BLK) {
+      const int x = i % PH, y = (i / PH) % PH, z = i / (PH * PH);
+      const int gx = wrapi(fx0 + x, a.nm), gy = wrapi(fy0 + y, a.nm), gz = wrapi(fz0 + z, a.nm);
+      ph[i] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
+    }
+  }
+}
+
+// own cells of the tile: counts, starts and the exclusive prefix (one wave does the scan)
+template <int MODE>
+__device__ __forceinline__ uint32_t own_cells(const MoveArgs& a, const TileGeom& g, uint32_t* pre, uint64_t* start,
+                                              uint32_t* wsum) {
+  uint32_t cntv = 0;
+  if (threadIdx.x < TC) {
+    const int s = threadIdx.x;
+    const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
+    if constexpr (MODE == 2) {
+      cntv = (uint32_t)(a.q * a.q * a.q);
+      start[s] = (uint64_t)c * cntv;
+    } else {
+      cntv = a.cnt[c];
+      start[s] = a.off[c];
+    }
+  }
+  return block_exclusive_scan(cntv, pre, TC, wsum);
+}
+
+template <int NCHI, int NNU, int MODE>
+__global__ __launch_bounds__(BLK) void k_move_count(MoveArgs a) {
+  __shared__ float ph[MODE == 0 ? PH * PH * PH : 1];
+  __shared__ uint32_t mcnt[TC * 27];
+  __shared__ unsigned long long mom[RC * 4];
+  __shared__ uint32_t pre[TC + 1];
+  __shared__ uint64_t start[TC];
+  __shared__ uint32_t wsum[BLK / 64];
+  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  load_potential<NCHI, MODE>(a, ph, g);
+  for (int i = threadIdx.x; i < TC * 27; i += BLK) mcnt[i] = 0u;
+  for (int i = threadIdx.x; i < RC * 4; i += BLK) mom[i] = 0ull;
+  const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
+  for (uint32_t i = threadIdx.x; i < total; i += BLK) {
+    const int s = find_cell(pre, TC, i);
+    const uint32_t li = i - pre[s];
+    const int64_t p = (int64_t)start[s] + li;
+    const Moved m = move_particle<NCHI, NNU, MODE>(a, ph, s, p, li, g);
+    const int dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
+    atomicAdd(&mcnt[s * 27 + dcode], 1u);
+    const int r = (s % T + 1 + m.k[0]) + RG * ((s / T) % T + 1 + m.k[1]) + RG * RG * (s / (T * T) + 1 + m.k[2]);
+    long long s2 = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double vd = (double)m.v[d];
+      const long long t1 = __double2ll_rn(vd * 4294967296.0);
+      s2 += __double2ll_rn(vd * vd * 16777216.0);
+      atomicAdd(&mom[r * 4 + d], (unsigned long long)t1);
+    }
+    atomicAdd(&mom[r * 4 + 3], (unsigned long long)s2);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < TC * 27; i += BLK) {
+    const int s = i / 27, d = i % 27;
+    const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
+    a.mig[d * a.nc3 + c] = mcnt[i];
+  }
+  for (int i = threadIdx.x; i < RC * 4; i += BLK) {
+    const unsigned long long v = mom[i];
+    if (v == 0ull) continue;
+    const int r = i / 4, q = i % 4;
+    const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
+    const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
+    const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[q * a.nc3 + c]), v);
+  }
+}
+
+template <int NNU>
+__device__ __forceinline__ int encode_nu(float u, const float* edges, int nedge, int vhalf) {
+  // number of edges <= u (upper bound), edges ascending
+  int lo = 0, hi = nedge;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (edges[mid] <= u) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - vhalf;
+}
+
+template <int NCHI, int NNU, int MODE>
+__global__ __launch_bounds__(BLK) void k_move_scatter(MoveArgs a) {
+  using CT = chi_t<NCHI>;
+  using NT = nu_t<NNU>;
+  __shared__ float ph[MODE == 0 ? PH * PH * PH : 1];
+  __shared__ uint32_t grp[TC * 27];
+  __shared__ uint32_t pre[TC + 1];
+  __shared__ uint64_t start[TC];
+  __shared__ uint32_t wsum[BLK / 64];
+  __shared__ float edges_lds[NNU == 1 ? 254 : 1];
+  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  load_potential<NCHI, MODE>(a, ph, g);
+  for (int i = threadIdx.x; i < TC * 27; i += BLK) grp[i] = 0u;
+  const int nedge = 2 * a.vhalf;
+  if constexpr (NNU == 1)
+    for (int i = threadIdx.x; i < nedge; i += BLK) edges_lds[i] = a.tedge[i];
+  const float* edges = (NNU == 1) ? edges_lds : a.tedge;
+  const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
+  CT* chi_n = static_cast<CT*>(a.chi_n);
+  NT* nu_n = static_cast<NT*>(a.nu_n);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (uint32_t base_i = 0; base_i < total; base_i += BLK) {
+    const uint32_t i = base_i + threadIdx.x;
+    const bool active = i < total;
+    Moved m{};
+    int s = 0, key = 0, dcode = 0;
+    if (active) {
+      s = find_cell(pre, TC, i);
+      const uint32_t li = i - pre[s];
+      const int64_t p = (int64_t)start[s] + li;
+      m = move_particle<NCHI, NNU, MODE>(a, ph, s, p, li, g);
+      dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
+      key = s * 27 + dcode;
+    }
+    // peers with the same (source cell, displacement) in this wave
+    unsigned long long peers = __ballot(active);
+#pragma unroll
+    for (int b = 0; b < 11; ++b) {
+      const bool bit = (key >> b) & 1;
+      const unsigned long long bb = __ballot(active && bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const int rin = __popcll(peers & lt);
+    const int leader = __ffsll((long long)peers) - 1;
+    uint32_t gbase = 0;
+    // waves take their turn in order so that ranks follow storage order
+    for (int w = 0; w < BLK / 64; ++w) {
+      if (w == wave && active && rin == 0) {
+        gbase = grp[key];
+        grp[key] = gbase + (uint32_t)__popcll(peers);
+      }
+      __syncthreads();
+    }
+    gbase = (uint32_t)__shfl((int)gbase, leader < 0 ? 0 : leader, 64);
+    if (active) {
+      const int ox = s % T, oy = (s / T) % T, oz = s / (T * T);
+      const int nx = wrapi(g.cx0 + ox + m.k[0], a.nc), ny = wrapi(g.cy0 + oy + m.k[1], a.nc);
+      const int nz = wrapi(g.cz0 + oz + m.k[2], a.nc);
+      const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
+      const uint64_t dst = a.off_n[cn] + a.slot[(int64_t)(26 - dcode) * a.nc3 + cn] + gbase + (uint32_t)rin;
+      if (dst >= (uint64_t)a.cap) {
+        set_flag(a.flags, FLAG_COUNT);
+        continue;
+      }
+      const float inv = a.vinv[cn];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float u = (m.v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
+        nu_n[d * a.cap + dst] = (NT)encode_nu<NNU>(u, edges, nedge, a.vhalf);
+        chi_n[d * a.cap + dst] = (CT)m.chi[d];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Link: per new cell, counts from the 27 source cells in offset order (z, y, x each -1, 0, +1),
+// the slot prefix per source offset, the mean velocity and the 3-D velocity variance.
+// ---------------------------------------------------------------------------------------------
+struct LinkArgs {
+  const uint32_t* mig;
+  uint32_t* slot;
+  uint32_t* cnt_n;
+  int64_t* mom;
+  float* vc_n;
+  double* dev;
+  uint64_t* blk_n;
+  int64_t* blk_q;
+  int nc;
+  int64_t nc3;
+  const uint32_t* cnt_direct;  // load path: counts given directly (no migration counts)
+};
+
+__global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) {
+  __shared__ unsigned long long sn[LINK_BLK];
+  __shared__ long long sq[LINK_BLK];
+  const int64_t c = (int64_t)blockIdx.x * LINK_BLK + threadIdx.x;
+  uint32_t n = 0;
+  long long q = 0;
+  if (c < a.nc3) {
+    if (a.cnt_direct) {
+      n = a.cnt_direct[c];
+    } else {
+      const int x = (int)(c % a.nc), y = (int)((c / a.nc) % a.nc), z = (int)(c / ((int64_t)a.nc * a.nc));
+      uint32_t run = 0;
+      for (int j = 0; j < 27; ++j) {
+        const int ox = j % 3 - 1, oy = (j / 3) % 3 - 1, oz = j / 9 - 1;
+        const int64_t src = wrapi(x + ox, a.nc) + (int64_t)a.nc * (wrapi(y + oy, a.nc) + (int64_t)a.nc * wrapi(z + oz, a.nc));
+        const uint32_t mcount = a.mig[(int64_t)(26 - j) * a.nc3 + src];
+        a.slot[(int64_t)j * a.nc3 + c] = run;
+        run += mcount;
+      }
+      n = run;
+    }
+    a.cnt_n[c] = n;
+    const long long s1x = a.mom[c], s1y = a.mom[a.nc3 + c], s1z = a.mom[2 * a.nc3 + c], s2 = a.mom[3 * a.nc3 + c];
+    a.mom[c] = 0;
+    a.mom[a.nc3 + c] = 0;
+    a.mom[2 * a.nc3 + c] = 0;
+    a.mom[3 * a.nc3 + c] = 0;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, dev = 0.0;
+    const double nd = (double)n;
+    if (n > 0) {
+      const double d1 = nd * 4294967296.0;
+      m0 = (double)s1x / d1;
+      m1 = (double)s1y / d1;
+      m2 = (double)s1z / d1;
+      const double d2 = nd * 16777216.0;
+      const double e2 = (double)s2 / d2;
+      double mm = m0 * m0;
+      mm = mm + m1 * m1;
+      mm = mm + m2 * m2;
+      dev = e2 - mm;
+      if (!(dev > 0.0)) dev = 0.0;
+    }
+    a.vc_n[c] = (float)m0;
+    a.vc_n[a.nc3 + c] = (float)m1;
+    a.vc_n[2 * a.nc3 + c] = (float)m2;
+    a.dev[c] = dev;
+    q = __double2ll_rn((dev * nd) * 1048576.0);
+  }
+  sn[threadIdx.x] = n;
+  sq[threadIdx.x] = q;
+  __syncthreads();
+  for (int s = LINK_BLK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sn[threadIdx.x] += sn[threadIdx.x + s];
+      sq[threadIdx.x] += sq[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.blk_n[blockIdx.x] = sn[0];
+    a.blk_q[blockIdx.x] = sq[0];
+  }
+}
+
+// single workgroup: exclusive scan of the per-block counts, global dispersion
+__global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* blk_n, const int64_t* blk_q, uint64_t* blk_off,
+                                                      int64_t nblk, uint64_t* off_end, int64_t n_expect,
+                                                      double* scal, uint32_t* flags) {
+  __shared__ unsigned long long ps[1024];
+  __shared__ long long pq[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (nblk + 1023) / 1024;
+  const int64_t b0 = tid * per, b1 = (b0 + per < nblk) ? b0 + per : nblk;
+  unsigned long long s = 0;
+  long long qs = 0;
+  for (int64_t b = b0; b < b1; ++b) {
+    s += blk_n[b];
+    qs += blk_q[b];
+  }
+  ps[tid] = s;
+  pq[tid] = qs;
+  __syncthreads();
+  // inclusive scan (Hillis-Steele) of ps; tree sum of pq
+  for (int o = 1; o < 1024; o <<= 1) {
+    unsigned long long add = (tid >= o) ? ps[tid - o] : 0ull;
+    __syncthreads();
+    ps[tid] += add;
+    __syncthreads();
+  }
+  unsigned long long run = ps[tid] - s;
+  for (int64_t b = b0; b < b1; ++b) {
+    blk_off[b] = run;
+    run += blk_n[b];
+  }
+  for (int o = 512; o > 0; o >>= 1) {
+    if (tid < o) pq[tid] += pq[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const unsigned long long total = ps[1023];
+    *off_end = total;
+    if ((int64_t)total != n_expect) atomicOr(flags, FLAG_COUNT);
+    double sg2 = (double)pq[0] / ((3.0 * (double)n_expect) * 1048576.0);
+    if (!(sg2 > 0.0)) sg2 = 8.673617379884035e-19;  // 2^-60
+    scal[0] = sg2;
+  }
+}
+
+struct FinArgs {
+  const uint32_t* cnt_n;
+  const uint64_t* blk_off;
+  uint64_t* off_n;
+  const double* dev;
+  const double* scal;
+  float* vs_n;
+  float* vinv;
+  int64_t nc3;
+  int sigma_mode;
+  double sq2pi;
+};
+
+__global__ __launch_bounds__(LINK_BLK) void k_finalize(FinArgs a) {
+  __shared__ uint32_t pre[LINK_BLK + 1];
+  __shared__ uint32_t wsum[LINK_BLK / 64];
+  const int64_t c = (int64_t)blockIdx.x * LINK_BLK + threadIdx.x;
+  const uint32_t n = (c < a.nc3) ? a.cnt_n[c] : 0u;
+  block_exclusive_scan(n, pre, LINK_BLK, wsum);
+  if (c >= a.nc3) return;
+  a.off_n[c] = a.blk_off[blockIdx.x] + pre[threadIdx.x];
+  const double sg2 = a.scal[0];
+  double s2c = sg2;
+  if (a.sigma_mode == CUBE_SIGMA_PER_CELL) {
+    s2c = a.dev[c] / 3.0;
+    if (n < 2 || s2c < sg2 * 9.5367431640625e-07) s2c = sg2;
+  }
+  const double sc = sqrt(s2c) * a.sq2pi;
+  a.vs_n[c] = (float)sc;
+  a.vinv[c] = (float)(1.0 / sc);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Load path: host particles -> codes, stable sort by cell, moments, encode
+// ---------------------------------------------------------------------------------------------
+struct LoadArgs {
+  const double* x;   // (n,3)
+  const double* v;   // (n,3)
+  int64_t n;
+  int nc, nchi;
+  uint32_t* key;
+  uint32_t* idx;
+  uint16_t* chi_tmp;  // 3 x n
+  float* v_tmp;       // 3 x n
+  uint32_t* cnt;
+  int64_t* mom;
+  int64_t nc3;
+  uint32_t* flags;
+};
+
+__global__ void k_load_codes(LoadArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int nb = 1 << (8 * a.nchi);
+  int cell[3];
+  for (int d = 0; d < 3; ++d) {
+    double xc = a.x[3 * i + d] * 0.25;
+    if (!(fabs(xc) < 1e15)) {
+      atomicOr(a.flags, FLAG_NONFINITE);
+      xc = 0.0;
+    }
+    if (xc < 0.0 || xc >= (double)a.nc) xc = xc - (double)a.nc * floor(xc / (double)a.nc);
+    int c = (int)floor(xc);
+    if (c >= a.nc) c -= a.nc;
+    if (c < 0) c = 0;
+    long long b = (long long)floor((xc - (double)c) * (double)nb);
+    b = b < 0 ? 0 : (b > nb - 1 ? nb - 1 : b);
+    cell[d] = c;
+    a.chi_tmp[d * a.n + i] = (uint16_t)b;
+  }
+  const uint32_t cid = (uint32_t)(cell[0] + a.nc * (cell[1] + a.nc * cell[2]));
+  a.key[i] = cid;
+  a.idx[i] = (uint32_t)i;
+  long long s2 = 0;
+  for (int d = 0; d < 3; ++d) {
+    const float vf = (float)a.v[3 * i + d];
+    a.v_tmp[d * a.n + i] = vf;
+    if (!(vf == vf) || fabsf(vf) >= 32768.0f) atomicOr(a.flags, FLAG_OVERFLOW);
+    const double vd = (double)vf;
+    atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cid]),
+              (unsigned long long)__double2ll_rn(vd * 4294967296.0));
+    s2 += __double2ll_rn(vd * vd * 16777216.0);
+  }
+  atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[3 * a.nc3 + cid]), (unsigned long long)s2);
+  atomicAdd(&a.cnt[cid], 1u);
+}
+
+template <int NCHI, int NNU>
+__global__ void k_load_encode(const uint32_t* key_sorted, const uint32_t* idx_sorted, const uint16_t* chi_tmp,
+                              const float* v_tmp, int64_t n, void* chi_out, void* nu_out, int64_t cap,
+                              const float* vc, const float* vinv, int64_t nc3, const float* edges, int vhalf) {
+  using CT = chi_t<NCHI>;
+  using NT = nu_t<NNU>;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t src = idx_sorted[j];
+  const int64_t c = key_sorted[j];
+  CT* co = static_cast<CT*>(chi_out);
+  NT* no = static_cast<NT*>(nu_out);
+  const float inv = vinv[c];
+  for (int d = 0; d < 3; ++d) {
+    co[d * cap + j] = (CT)chi_tmp[d * n + src];
+    const float u = (v_tmp[d * n + src] - vc[d * nc3 + c]) * inv;
+    no[d * cap + j] = (NT)encode_nu<NNU>(u, edges, 2 * vhalf, vhalf);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// White noise: Philox4x32-10 (Salmon et al. 2011) keyed by (seed, lattice index), Box-Muller.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox_round(uint32_t* c, uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+  const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+  const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+  const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+  c[0] = n0;
+  c[1] = lo1;
+  c[2] = n2;
+  c[3] = lo0;
+}
+
+__global__ void k_noise(float* out, int n, int64_t pitch_f, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)n * n * n;
+  if (i >= total) return;
+  uint32_t c[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, 0u};
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    philox_round(c, k0, k1);
+  }
+  const double u0 = ((double)c[0] + 0.5) * 2.3283064365386962890625e-10;
+  const double u1 = ((double)c[1] + 0.5) * 2.3283064365386962890625e-10;
+  const double w = sqrt(-2.0 * log(u0)) * cos(6.283185307179586 * u1);
+  const int64_t x = i % n, y = (i / n) % n, z = i / ((int64_t)n * n);
+  out[(z * n + y) * pitch_f + x] = (float)w;
+}
+
+}  // namespace
+
+// =============================================================================================
+// host launchers
+// =============================================================================================
+#define CUBE_XV_DISPATCH(nchi, nnu, CALL)                                     \
+  do {                                                                        \
+    if ((nchi) == 1 && (nnu) == 1) CALL(1, 1);                                \
+    else if ((nchi) == 1 && (nnu) == 2) CALL(1, 2);                           \
+    else if ((nchi) == 2 && (nnu) == 1) CALL(2, 1);                           \
+    else CALL(2, 2);                                                          \
+  } while (0)
+
+void launch_deposit(Sim& s, hipStream_t st) {
+  DepArgs a;
+  a.chi = s.chi[s.cur];
+  a.cnt = s.cnt[s.cur];
+  a.off = s.off[s.cur];
+  a.cap = s.capacity;
+  a.mesh = s.mesh;
+  a.pitch_f = (int64_t)s.mesh_plan.row_floats();
+  a.nm = s.nm;
+  a.nc = s.nc;
+  a.nt = s.nc / T;
+  a.inv_mean = (double)s.nm * (double)s.nm * (double)s.nm / ((double)s.n * ldexp(1.0, 3 * (8 * s.nchi - 1)));
+  const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
+  if (s.nchi == 1) k_deposit<1><<<grid, BLK, 0, st>>>(a);
+  else k_deposit<2><<<grid, BLK, 0, st>>>(a);
+  CUBE_HIP(hipGetLastError());
+}
+
+static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipStream_t st) {
+  LinkArgs l;
+  l.mig = s.mig;
+  l.slot = s.slot;
+  l.cnt_n = s.cnt[nxt];
+  l.mom = s.mom;
+  l.vc_n = s.vc[nxt];
+  l.dev = s.dev;
+  l.blk_n = s.blk_n;
+  l.blk_q = s.blk_q;
+  l.nc = s.nc;
+  l.nc3 = s.nc3;
+  l.cnt_direct = cnt_direct;
+  k_link<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(l);
+  CUBE_HIP(hipGetLastError());
+  k_scan_blocks<<<1, 1024, 0, st>>>(s.blk_n, s.blk_q, s.blk_off, s.nblk, s.off[nxt] + s.nc3, s.n, s.scal, s.flags);
+  CUBE_HIP(hipGetLastError());
+  FinArgs f;
+  f.cnt_n = s.cnt[nxt];
+  f.blk_off = s.blk_off;
+  f.off_n = s.off[nxt];
+  f.dev = s.dev;
+  f.scal = s.scal;
+  f.vs_n = s.vs[nxt];
+  f.vinv = s.vinv;
+  f.nc3 = s.nc3;
+  f.sigma_mode = s.p.sigma_mode;
+  f.sq2pi = std::sqrt(2.0 / M_PI);
+  k_finalize<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(f);
+  CUBE_HIP(hipGetLastError());
+}
+
+void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
+                 hipEvent_t* evs) {
+  const int nxt = s.cur ^ 1;
+  MoveArgs a{};
+  a.chi = s.chi[s.cur];
+  a.nu = s.nu[s.cur];
+  a.cnt = s.cnt[s.cur];
+  a.off = s.off[s.cur];
+  a.vc = s.vc[s.cur];
+  a.vs = s.vs[s.cur];
+  a.chi_n = s.chi[nxt];
+  a.nu_n = s.nu[nxt];
+  a.off_n = s.off[nxt];
+  a.vc_n = s.vc[nxt];
+  a.vinv = s.vinv;
+  a.cap = s.capacity;
+  a.mesh = s.mesh;
+  a.pitch_f = (int64_t)s.mesh_plan.row_floats();
+  a.nm = s.nm;
+  a.nc = s.nc;
+  a.nt = s.nc / T;
+  a.nc3 = s.nc3;
+  a.kf = kfac;
+  a.df = dfac;
+  a.tdec = s.tdec;
+  a.tedge = s.tedge;
+  a.vhalf = (s.vm - 1) / 2;
+  a.mig = s.mig;
+  a.slot = s.slot;
+  a.mom = s.mom;
+  a.flags = s.flags;
+  if (mode == 2) {
+    a.psi0 = psi[0];
+    a.psi1 = psi[1];
+    a.psi2 = psi[2];
+    a.lat_pitch_f = (int64_t)s.lat_plan.row_floats();
+    a.np = s.np;
+    a.q = s.np / s.nc;
+    a.vfac = vfac;
+    a.lunit = (float)(2.0 / (double)a.q);
+  }
+  const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
+#define CUBE_COUNT(X, V)                                                      \
+  do {                                                                        \
+    if (mode == 0) k_move_count<X, V, 0><<<grid, BLK, 0, st>>>(a);            \
+    else if (mode == 1) k_move_count<X, V, 1><<<grid, BLK, 0, st>>>(a);       \
+    else k_move_count<X, V, 2><<<grid, BLK, 0, st>>>(a);                      \
+  } while (0)
+#define CUBE_SCATTER(X, V)                                                    \
+  do {                                                                        \
+    if (mode == 0) k_move_scatter<X, V, 0><<<grid, BLK, 0, st>>>(a);          \
+    else if (mode == 1) k_move_scatter<X, V, 1><<<grid, BLK, 0, st>>>(a);     \
+    else k_move_scatter<X, V, 2><<<grid, BLK, 0, st>>>(a);                    \
+  } while (0)
+  CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_COUNT);
+  CUBE_HIP(hipGetLastError());
+  if (evs) CUBE_HIP(hipEventRecord(evs[0], st));
+  link_scan_finalize(s, nxt, nullptr, st);
+  if (evs) CUBE_HIP(hipEventRecord(evs[1], st));
+  CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_SCATTER);
+  CUBE_HIP(hipGetLastError());
+#undef CUBE_COUNT
+#undef CUBE_SCATTER
+  s.cur = nxt;
+}
+
+void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, hipStream_t st) {
+  // scratch for the load path
+  const int nxt = s.cur ^ 1;
+  uint32_t* key = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * n * 4));
+  uint32_t* idx = key + n;
+  uint32_t* key2 = key + 2 * n;
+  uint32_t* idx2 = key + 3 * n;
+  uint16_t* chi_tmp = static_cast<uint16_t*>(s.dmalloc(sizeof(uint16_t) * 3 * n));
+  float* v_tmp = static_cast<float*>(s.dmalloc(sizeof(float) * 3 * n));
+  CUBE_HIP(hipMemsetAsync(s.cnt[nxt], 0, sizeof(uint32_t) * s.nc3, st));
+  LoadArgs a;
+  a.x = dx;
+  a.v = dx + 3 * n;
+  a.n = n;
+  a.nc = s.nc;
+  a.nchi = s.nchi;
+  a.key = key;
+  a.idx = idx;
+  a.chi_tmp = chi_tmp;
+  a.v_tmp = v_tmp;
+  a.cnt = s.cnt[nxt];
+  a.mom = s.mom;
+  a.nc3 = s.nc3;
+  a.flags = s.flags;
+  if (n > 0) {
+    k_load_codes<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a);
+    CUBE_HIP(hipGetLastError());
+  }
+  // stable radix sort of (cell id, input index)
+  size_t tmp_bytes = 0;
+  const unsigned end_bit = 32;
+  CUBE_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, key, key2, idx, idx2, (size_t)n, 0, end_bit, st));
+  void* tmp = s.dmalloc(tmp_bytes > 0 ? tmp_bytes : 16);
+  CUBE_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, key, key2, idx, idx2, (size_t)n, 0, end_bit, st));
+  link_scan_finalize(s, nxt, s.cnt[nxt], st);
+#define CUBE_ENC(X, V)                                                                                       \
+  k_load_encode<X, V><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(key2, idx2, chi_tmp, v_tmp, n, s.chi[nxt], \
+                                                                   s.nu[nxt], s.capacity, s.vc[nxt], s.vinv, \
+                                                                   s.nc3, s.tedge, (s.vm - 1) / 2)
+  if (n > 0) {
+    CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_ENC);
+    CUBE_HIP(hipGetLastError());
+  }
+#undef CUBE_ENC
+  CUBE_HIP(hipStreamSynchronize(st));
+  s.dfree(tmp);
+  s.dfree(v_tmp);
+  s.dfree(chi_tmp);
+  s.dfree(key);
+  s.cur = nxt;
+}
+
+void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st) {
+  const int64_t total = (int64_t)pl.n * pl.n * pl.n;
+  k_noise<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(out, pl.n, (int64_t)pl.row_floats(), seed);
+  CUBE_HIP(hipGetLastError());
+}
+
+}  // namespace cube

@@ -1,0 +1,146 @@
+"""GPU path vs the oracle through the C ABI: bit-exact codes, counts, order and density from
+identical inputs; Poisson solve within 1e-5; full runs within the P(k) tolerance."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import pm, twin
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("cnt", "chi", "nu", "vc", "vs")
+
+
+@pytest.fixture(scope="module")
+def Sim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1712_06121_amd import Sim as S
+    return S
+
+
+def assert_state_equal(got: dict, ref: twin.State, tag=""):
+    for key in KEYS:
+        a, b = got[key], getattr(ref, key)
+        assert a.shape == b.shape, (tag, key, a.shape, b.shape)
+        if not np.array_equal(a, b):
+            bad = np.argwhere(a != b)
+            raise AssertionError(f"{tag} {key}: {len(bad)} mismatches, first {bad[:5].tolist()}")
+
+
+def twin_state(d: dict, nc, nchi, nnu) -> twin.State:
+    return twin.State(nc, nchi, nnu, d["cnt"], d["chi"], d["nu"], d["vc"], d["vs"])
+
+
+CODECS = [(1, 1, 1), (2, 1, 1), (1, 2, 0), (2, 2, 1)]
+
+
+@pytest.mark.parametrize("nchi,nnu,mode", CODECS)
+def test_load_bit_exact(Sim, nchi, nnu, mode):
+    nm, nc, n = 64, 16, 30011
+    x, v = synth.particle_cloud(21 + nchi + 2 * nnu, n, nm)
+    ref = twin.load(x, v, nc, nchi, nnu, mode)
+    with Sim(32, nm, 100.0, x_bytes=nchi, v_bytes=nnu, sigma_mode=mode, capacity=n) as sim:
+        sim.load_particles(x, v)
+        assert_state_equal(sim.get_state(), ref, f"load x{nchi}v{nnu}")
+
+
+def test_tables_match(Sim):
+    for nnu in (1, 2):
+        with Sim(32, 64, 100.0, v_bytes=nnu) as sim:
+            dec, edg = sim.get_tables()
+        assert np.array_equal(dec, twin.decode_table(nnu))
+        assert np.array_equal(edg, twin.edge_table(nnu))
+
+
+@pytest.mark.parametrize("nchi", [1, 2])
+@pytest.mark.parametrize("nm", [32, 64, 128])
+def test_deposit_bit_exact(Sim, nchi, nm):
+    nc = nm // 4
+    n = 5 * nm**3 // 16 + 7
+    x, v = synth.particle_cloud(31 + nm, n, nm, clump_frac=0.4)
+    ref = twin.load(x, v, nc, nchi, 1)
+    with Sim(32 if nm < 128 else 32, nm, 100.0, x_bytes=nchi, capacity=n) as sim:
+        sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
+        sim.stage_deposit()
+        got = sim.get_mesh()
+    exp = twin.delta_from_rho(twin.deposit_int(ref, nm), ref.n, nchi)
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("nm", [32, 64, 256])
+def test_solve_within_tolerance(Sim, nm):
+    nc = nm // 4
+    rng = np.random.default_rng(nm)
+    delta = rng.normal(size=(nm, nm, nm)).astype(np.float32)
+    with Sim(32 if nm < 256 else 64, nm, 100.0, omega_m=0.3) as sim:
+        sim.set_mesh(delta)
+        sim.stage_solve()
+        phi = sim.get_mesh()
+    ref = pm.poisson(delta.astype(np.float64), 0.3)
+    assert np.linalg.norm(phi - ref) / np.linalg.norm(ref) < 1e-5
+    g = pm.gradient4(phi.astype(np.float64))
+    gr = pm.gradient4(ref)
+    num = np.sqrt(sum(((a - b) ** 2).sum() for a, b in zip(g, gr)))
+    den = np.sqrt(sum((b**2).sum() for b in gr))
+    assert num / den < 1e-5
+
+
+def test_solve_plane_wave_exact(Sim):
+    nm, om = 128, 0.3
+    i = np.arange(nm)
+    z, y, x = np.meshgrid(i, i, i, indexing="ij")
+    kv = 2 * np.pi * np.array([3, -5, 7]) / nm
+    arg = kv[0] * x + kv[1] * y + kv[2] * z
+    with Sim(32, nm, 100.0, omega_m=om) as sim:
+        sim.set_mesh(np.cos(arg).astype(np.float32))
+        sim.stage_solve()
+        phi = sim.get_mesh()
+    exact = -1.5 * om * np.cos(arg) / (kv**2).sum()
+    assert np.abs(phi - exact).max() < 1e-5 * np.abs(exact).max()
+
+
+MOVE_CASES = [
+    (1, 1, 1, 64, 40000, 2.0),
+    (2, 1, 1, 64, 30000, 1.0),
+    (1, 2, 0, 32, 9000, 3.0),
+    (2, 2, 1, 64, 25000, 0.5),
+    (1, 1, 1, 128, 150000, 1.5),
+]
+
+
+@pytest.mark.parametrize("nchi,nnu,mode,nm,n,vscale", MOVE_CASES)
+def test_move_bit_exact(Sim, nchi, nnu, mode, nm, n, vscale):
+    nc = nm // 4
+    x, v = synth.particle_cloud(41 + nm + nchi, n, nm, vscale=vscale, clump_frac=0.5, clump_radius=1.0)
+    st = twin.load(x, v, nc, nchi, nnu, mode)
+    phi = synth.smooth_potential(7 + nm, nm, amp=2.0)
+    kf, df = np.float32(-1.3 / 12.0), np.float32(0.9)
+    exp, info = twin.move(st, phi, kf, df, sigma_mode=mode, return_info=True)
+    assert not info["cfl"]
+    moved = (info["dcode"] != 13).mean()
+    assert moved > 0.02  # many particles change cell, some cross the periodic boundary
+    with Sim(32, nm, 100.0, x_bytes=nchi, v_bytes=nnu, sigma_mode=mode, capacity=n) as sim:
+        sim.set_state(st.cnt, st.chi, st.nu, st.vc, st.vs)
+        sim.set_mesh(phi)
+        sim.stage_move(kf, df)
+        got = sim.get_state()
+        assert_state_equal(got, exp, f"move x{nchi}v{nnu}")
+        # a second move from the GPU's own output stays bit-exact
+        sim.stage_move(kf, df)
+        got2 = sim.get_state()
+    exp2 = twin.move(exp, phi, kf, df, sigma_mode=mode)
+    assert_state_equal(got2, exp2, "second move")
+
+
+def test_cfl_violation_reported(Sim):
+    from paper_1712_06121_amd import CubeError
+    nm, nc, n = 64, 16, 5000
+    x, v = synth.particle_cloud(5, n, nm, vscale=1.0)
+    with Sim(32, nm, 100.0, capacity=n) as sim:
+        sim.load_particles(x, v)
+        sim.set_mesh(np.zeros((nm,) * 3, np.float32))
+        with pytest.raises(CubeError) as e:
+            sim.stage_move(0.0, 50.0)
+        assert e.value.code == -5
