@@ -169,12 +169,13 @@ int cube_get_schedule(const cube_sim* sim, double* drift0, double* kick, double*
 /* Device memory held by the simulation, in bytes. */
 int64_t cube_device_bytes(const cube_sim* sim);
 
-/* Time of each kernel class of the last cube_step call measured with HIP events on the
- * simulation's stream (milliseconds, summed over the steps of that call): index 0 deposit,
- * 1 FFT + Green's function, 2 move count pass, 3 link + scan, 4 move scatter pass. Requires
- * profiling enabled with cube_set_profiling(sim, 1). */
+/* Average time per step of each kernel of the last cube_step call, measured with HIP events on
+ * the simulation's stream (milliseconds). ms9: 0 deposit, 1 FFT x pass, 2 FFT y pass,
+ * 3 fused z pass with the Green's function, 4 inverse y pass, 5 inverse x pass, 6 move count
+ * pass, 7 link + scan + statistics, 8 move scatter pass. Profiling must be enabled with
+ * cube_set_profiling(sim, 1); it adds one host synchronisation per step. */
 int cube_set_profiling(cube_sim* sim, int enable);
-int cube_get_timings(const cube_sim* sim, double* ms5);
+int cube_get_timings(const cube_sim* sim, double* ms9);
 
 #ifdef __cplusplus
 }

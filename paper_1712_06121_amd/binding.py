@@ -283,7 +283,11 @@ class Sim:
     def set_profiling(self, on: bool = True):
         self._check(self._lib.cube_set_profiling(self._h, int(on)))
 
+    TIMING_NAMES = ("deposit", "fft_x", "fft_y", "fft_z_green", "fft_y_inv", "fft_x_inv", "move_count",
+                    "link_scan", "move_scatter")
+
     def get_timings(self) -> np.ndarray:
-        out = np.empty(5)
+        """Average milliseconds per step of each kernel (order of TIMING_NAMES)."""
+        out = np.empty(9)
         self._check(self._lib.cube_get_timings(self._h, _ptr(out)))
         return out

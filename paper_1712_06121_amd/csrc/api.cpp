@@ -125,7 +125,7 @@ void require_particles(const Sim& s) {
 }
 
 // psi buffers for the initial conditions; returns the transformed noise buffer
-void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps) {
+void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps, bool use_state_buffer) {
   const size_t fbytes = s.lat_plan.field_floats() * sizeof(float);
   float* wk = nullptr;
   if (s.lat_plan.n == s.mesh_plan.n) {
@@ -135,6 +135,10 @@ void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps) {
     temps.push_back(wk);
   }
   for (int d = 0; d < 3; ++d) {
+    if (d == 0 && use_state_buffer && s.pbytes >= fbytes) {
+      psi[d] = static_cast<float*>(s.chi[s.cur]);  // the lattice pre-state reads no stored codes
+      continue;
+    }
     psi[d] = static_cast<float*>(s.dmalloc(fbytes));
     temps.push_back(psi[d]);
   }
@@ -145,10 +149,10 @@ void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps) {
   const int64_t ntab = 3LL * h * h + 1;
   std::vector<float> tab(ntab, 0.0f);
   const double box = s.p.box, np3 = (double)s.np * s.np * s.np;
-  const double ai = s.p.a_init;
+  const double di = s.cosmo.D(s.p.a_init);
   for (int64_t n2 = 1; n2 < ntab; ++n2) {
     const double k = 2.0 * M_PI * std::sqrt((double)n2) / box;
-    const double amp = std::sqrt(np3 * s.cosmo.pk(k, ai) / (box * box * box));
+    const double amp = std::sqrt(np3 * s.cosmo.pk_shape(k) * di * di / (box * box * box));
     tab[n2] = (float)(amp * (double)s.nm / (2.0 * M_PI * (double)n2 * np3));
   }
   float* dtab = static_cast<float*>(s.dmalloc(sizeof(float) * ntab));
@@ -296,7 +300,7 @@ int cube_init_ic(cube_sim* sim) {
     std::vector<void*> temps;
     float* psi[3];
     float* wk = nullptr;
-    cube::ic_fields(s, psi, &wk, temps);
+    cube::ic_fields(s, psi, &wk, temps, true);
     s.n = (int64_t)s.np * s.np * s.np;
     if (s.n > s.capacity) throw Error{CUBE_E_CAPACITY, "np_side^3 exceeds the capacity"};
     const double a = s.p.a_init;
@@ -318,7 +322,7 @@ int cube_get_ic_displacement(cube_sim* sim, float* host_dst) {
     std::vector<void*> temps;
     float* psi[3];
     float* wk = nullptr;
-    cube::ic_fields(s, psi, &wk, temps);
+    cube::ic_fields(s, psi, &wk, temps, false);
     const size_t pitch = s.lat_plan.row_floats() * sizeof(float);
     const size_t np3 = (size_t)s.np * s.np * s.np;
     for (int d = 0; d < 3; ++d)
@@ -357,8 +361,10 @@ int cube_step(cube_sim* sim, int32_t k) {
   int rc = CUBE_OK;
   CUBE_GUARD(sim, {
     cube::require_particles(s);
-    if (s.profiling)
+    if (s.profiling) {
       for (double& t : s.timings) t = 0.0;
+      s.timing_calls = 0;
+    }
     for (int i = 0; i < k; ++i) {
       if (s.steps_done >= s.p.n_steps) {
         rc = CUBE_DONE;
@@ -369,24 +375,23 @@ int cube_step(cube_sim* sim, int32_t k) {
         s.half_drift_done = true;
       }
       const int j = s.steps_done;
+      // profiling events: [0,1] deposit, [2..7] five FFT passes, [8..11] count, link, scatter
       hipEvent_t* ev = s.profiling ? s.ev : nullptr;
       if (ev) CUBE_HIP(hipEventRecord(ev[0], s.stream));
       cube::launch_deposit(s, s.stream);
       if (ev) CUBE_HIP(hipEventRecord(ev[1], s.stream));
-      cube::fft_solve_poisson(s.mesh_plan, s.mesh, cube::gconst(s), s.stream);
-      if (ev) CUBE_HIP(hipEventRecord(ev[2], s.stream));
+      cube::fft_solve_poisson(s.mesh_plan, s.mesh, cube::gconst(s), s.stream, ev ? ev + 2 : nullptr);
       cube::launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream,
-                        ev ? ev + 3 : nullptr);
+                        ev ? ev + 8 : nullptr);
       if (ev) {
-        CUBE_HIP(hipEventRecord(ev[5], s.stream));
-        CUBE_HIP(hipEventSynchronize(ev[5]));
-        float ms[5];
-        CUBE_HIP(hipEventElapsedTime(&ms[0], ev[0], ev[1]));
-        CUBE_HIP(hipEventElapsedTime(&ms[1], ev[1], ev[2]));
-        CUBE_HIP(hipEventElapsedTime(&ms[2], ev[2], ev[3]));
-        CUBE_HIP(hipEventElapsedTime(&ms[3], ev[3], ev[4]));
-        CUBE_HIP(hipEventElapsedTime(&ms[4], ev[4], ev[5]));
-        for (int q = 0; q < 5; ++q) s.timings[q] += ms[q];
+        CUBE_HIP(hipEventSynchronize(ev[11]));
+        const int pairs[9][2] = {{0, 1}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {8, 9}, {9, 10}, {10, 11}};
+        for (int q = 0; q < 9; ++q) {
+          float ms = 0.f;
+          CUBE_HIP(hipEventElapsedTime(&ms, ev[pairs[q][0]], ev[pairs[q][1]]));
+          s.timings[q] += ms;
+        }
+        s.timing_calls++;
       }
       s.steps_done++;
     }
@@ -580,9 +585,9 @@ int cube_set_profiling(cube_sim* sim, int enable) {
   return CUBE_OK;
 }
 
-int cube_get_timings(const cube_sim* sim, double* ms5) {
-  if (!sim || !ms5) return CUBE_E_INVALID;
-  for (int i = 0; i < 5; ++i) ms5[i] = sim->s.timings[i];
+int cube_get_timings(const cube_sim* sim, double* ms9) {
+  if (!sim || !ms9) return CUBE_E_INVALID;
+  for (int i = 0; i < 9; ++i) ms9[i] = sim->s.timing_calls ? sim->s.timings[i] / sim->s.timing_calls : 0.0;
   return CUBE_OK;
 }
 

@@ -6,7 +6,7 @@
 #include <functional>
 #include <vector>
 
-#include "cube_internal.h"
+#include "cosmo.h"
 
 namespace cube {
 namespace {
@@ -49,16 +49,23 @@ const GL& gl20() {
   return g;
 }
 
-double adapt(const std::function<double(double)>& f, double a, double b, double whole, double tol, int depth) {
+// Adaptive bisection: accept when two half-interval rules agree with the whole-interval rule to
+// the relative tolerance or to the absolute floor `atol` (needed where the integral cancels).
+double adapt(const std::function<double(double)>& f, double a, double b, double whole, double rtol, double atol,
+             int depth) {
   const double m = 0.5 * (a + b);
   const double l = gl20().apply(f, a, m), r = gl20().apply(f, m, b);
-  if (depth > 40 || std::fabs(l + r - whole) <= tol * std::fabs(l + r) + 1e-300) return l + r;
-  return adapt(f, a, m, l, tol, depth + 1) + adapt(f, m, b, r, tol, depth + 1);
+  const double err = std::fabs(l + r - whole);
+  if (depth >= 30 || err <= rtol * std::fabs(l + r) || err <= atol) return l + r;
+  return adapt(f, a, m, l, rtol, 0.5 * atol, depth + 1) + adapt(f, m, b, r, rtol, 0.5 * atol, depth + 1);
 }
 
-double integrate(const std::function<double(double)>& f, double a, double b, double tol = 1e-13) {
+double integrate(const std::function<double(double)>& f, double a, double b, double rtol = 1e-13,
+                 double atol = 0.0) {
   if (a == b) return 0.0;
-  return adapt(f, a, b, gl20().apply(f, a, b), tol, 0);
+  const double whole = gl20().apply(f, a, b);
+  const double floor_abs = atol > 0.0 ? atol : 1e-15 * std::fabs(whole);
+  return adapt(f, a, b, whole, rtol, floor_abs, 0);
 }
 
 double tophat(double x) {
@@ -106,10 +113,14 @@ double Cosmo::transfer(double k) const {
   return t1 * std::pow(poly, -0.25);
 }
 
-double Cosmo::pk(double k, double a) const {
+double Cosmo::pk_shape(double k) const {
   const double t = transfer(k);
+  return amp * std::pow(k, ns) * t * t;
+}
+
+double Cosmo::pk(double k, double a) const {
   const double d = D(a);
-  return amp * std::pow(k, ns) * t * t * d * d;
+  return pk_shape(k) * d * d;
 }
 
 void Cosmo::init() {
@@ -125,10 +136,15 @@ void Cosmo::init() {
   };
   const double lo = std::log(1e-6), hi = std::log(300.0);
   const int pieces = 200;
+  double rough = 0.0;
+  for (int i = 0; i < pieces; ++i) {
+    const double a0 = lo + (hi - lo) * i / pieces, a1 = lo + (hi - lo) * (i + 1) / pieces;
+    rough += std::fabs(gl20().apply(integrand, a0, a1));
+  }
   double s = 0.0;
   for (int i = 0; i < pieces; ++i) {
     const double a0 = lo + (hi - lo) * i / pieces, a1 = lo + (hi - lo) * (i + 1) / pieces;
-    s += integrate(integrand, a0, a1, 1e-12);
+    s += integrate(integrand, a0, a1, 1e-12, 1e-15 * rough / pieces);
   }
   s /= 2.0 * M_PI * M_PI;
   amp = sigma8 * sigma8 / s;

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/cube.h"
+#include "cosmo.h"
 
 namespace cube {
 
@@ -44,21 +45,6 @@ struct FFTPlan {
   float* k2 = nullptr;     // (2 pi f(t) / n)^2 with f the signed frequency of index t (device)
   size_t field_floats() const { return (size_t)n * n * pitch_c * 2; }
   size_t row_floats() const { return (size_t)pitch_c * 2; }
-};
-
-// ---- host cosmology (FP64) -----------------------------------------------------------------
-struct Cosmo {
-  double om, ol, ok, h, sigma8, ns;
-  double d_norm = 1.0, amp = 1.0;
-  double E(double a) const;
-  double growth_unnorm(double a) const;
-  double D(double a) const { return growth_unnorm(a) / d_norm; }
-  double f(double a) const;
-  double kick(double a0, double a1) const;
-  double drift(double a0, double a1) const;
-  double transfer(double k) const;
-  double pk(double k, double a) const;  // linear P(k) at a, (Mpc/h)^3
-  void init();
 };
 
 // ---- simulation ------------------------------------------------------------------------------
@@ -118,10 +104,11 @@ struct Sim {
   double a_now = 0.0;
   bool have_particles = false;
 
-  // profiling
+  // profiling: per-kernel event pairs recorded on the simulation's stream
   bool profiling = false;
-  hipEvent_t ev[12] = {};
-  double timings[5] = {0, 0, 0, 0, 0};
+  hipEvent_t ev[16] = {};
+  double timings[16] = {};
+  int timing_calls = 0;
 
   size_t pbytes = 0;  // bytes of one particle-state buffer (chi and nu planes)
 
@@ -135,7 +122,8 @@ struct Sim {
 void fft_plan_create(Sim& s, FFTPlan& pl, int n);
 void fft_plan_destroy(Sim& s, FFTPlan& pl);
 void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st);
-void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st);
+// evs (optional): 6 events recorded before the first pass and after each of the five passes
+void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs = nullptr);
 void fft_power(const FFTPlan& pl, float* data, double* acc, hipStream_t st);
 // initial conditions: psi_d = IFFT( i n_d tab[|n|^2] W ) with W the transformed noise
 void fft_ic_component(const FFTPlan& pl, const float* wk, float* out, const float* tab, int dim,

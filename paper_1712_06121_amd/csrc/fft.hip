@@ -348,13 +348,19 @@ void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const Co
 }
 
 template <int N>
-void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st) {
+void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st, hipEvent_t* ev) {
   ColArgs a{pl.k2, gconst, nullptr, nullptr, 0, N / 2};
+  if (ev) CUBE_HIP(hipEventRecord(ev[0], st));
   run_x<N>(pl, d, true, st);
+  if (ev) CUBE_HIP(hipEventRecord(ev[1], st));
   run_col<N, COL_FWD>(pl, d, d, 1, a, st);
+  if (ev) CUBE_HIP(hipEventRecord(ev[2], st));
   run_col<N, COL_GREEN>(pl, d, d, 2, a, st);
+  if (ev) CUBE_HIP(hipEventRecord(ev[3], st));
   run_col<N, COL_INV>(pl, d, d, 1, a, st);
+  if (ev) CUBE_HIP(hipEventRecord(ev[4], st));
   run_x<N>(pl, d, false, st);
+  if (ev) CUBE_HIP(hipEventRecord(ev[5], st));
 }
 
 template <int N>
@@ -427,8 +433,8 @@ void fft_plan_destroy(Sim& s, FFTPlan& pl) {
   pl.k2 = nullptr;
 }
 
-void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st) {
-#define CUBE_CALL(N) solve_n<N>(pl, data, gconst, st)
+void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs) {
+#define CUBE_CALL(N) solve_n<N>(pl, data, gconst, st, evs)
   CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
 #undef CUBE_CALL
 }

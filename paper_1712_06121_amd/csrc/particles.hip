@@ -742,10 +742,11 @@ __device__ __forceinline__ void philox_round(uint32_t* c, uint32_t k0, uint32_t 
   c[3] = lo0;
 }
 
+// grid: x covers one z plane of n^2 points, y = z (keeps each grid dimension below 2^32 items)
 __global__ void k_noise(float* out, int n, int64_t pitch_f, uint64_t seed) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)n * n * n;
-  if (i >= total) return;
+  const int64_t ixy = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ixy >= (int64_t)n * n) return;
+  const int64_t i = (int64_t)blockIdx.y * n * n + ixy;
   uint32_t c[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u, 0u};
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   for (int r = 0; r < 10; ++r) {
@@ -879,13 +880,15 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
     else if (mode == 1) k_move_scatter<X, V, 1><<<grid, BLK, 0, st>>>(a);     \
     else k_move_scatter<X, V, 2><<<grid, BLK, 0, st>>>(a);                    \
   } while (0)
+  if (evs) CUBE_HIP(hipEventRecord(evs[0], st));
   CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_COUNT);
   CUBE_HIP(hipGetLastError());
-  if (evs) CUBE_HIP(hipEventRecord(evs[0], st));
-  link_scan_finalize(s, nxt, nullptr, st);
   if (evs) CUBE_HIP(hipEventRecord(evs[1], st));
+  link_scan_finalize(s, nxt, nullptr, st);
+  if (evs) CUBE_HIP(hipEventRecord(evs[2], st));
   CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_SCATTER);
   CUBE_HIP(hipGetLastError());
+  if (evs) CUBE_HIP(hipEventRecord(evs[3], st));
 #undef CUBE_COUNT
 #undef CUBE_SCATTER
   s.cur = nxt;
@@ -944,8 +947,9 @@ void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, h
 }
 
 void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st) {
-  const int64_t total = (int64_t)pl.n * pl.n * pl.n;
-  k_noise<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(out, pl.n, (int64_t)pl.row_floats(), seed);
+  const int64_t plane = (int64_t)pl.n * pl.n;
+  const dim3 grid((unsigned)((plane + 255) / 256), (unsigned)pl.n);
+  k_noise<<<grid, 256, 0, st>>>(out, pl.n, (int64_t)pl.row_floats(), seed);
   CUBE_HIP(hipGetLastError());
 }
 

@@ -8,21 +8,23 @@ from __future__ import annotations
 
 import numpy as np
 
-# Workloads (box in Mpc/h; particles, fine mesh and coarse cells per side).
+# Workloads (box in Mpc/h; particles, fine mesh and coarse cells per side). The schedules are
+# uniform in a (spacing 1): with a fixed step count this keeps the per-step drift roughly constant
+# in the linear regime, above the resolution of 1-byte positions.
 WORKLOADS = {
     "c1_pm32": dict(np_side=32, nm_side=64, nc_side=16, box=100.0, x_bytes=1, v_bytes=1,
                     omega_m=1.0, omega_l=0.0, h=0.7, sigma8=0.8, n_s=1.0,
-                    a_init=0.02, a_final=1.0, n_steps=50, seed=1),
+                    a_init=0.02, a_final=1.0, n_steps=50, spacing=1, seed=1),
     "c2_pm128": dict(np_side=128, nm_side=256, nc_side=64, box=200.0, x_bytes=2, v_bytes=1,
                      omega_m=0.3, omega_l=0.7, h=0.7, sigma8=0.8, n_s=1.0,
-                     a_init=0.02, a_final=1.0, n_steps=100, seed=2),
+                     a_init=0.02, a_final=1.0, n_steps=100, spacing=1, seed=2),
     "c3_pm2048": dict(np_side=2048, nm_side=2048, nc_side=512, box=2000.0, x_bytes=1, v_bytes=1,
                       omega_m=0.3, omega_l=0.7, h=0.7, sigma8=0.8, n_s=1.0,
-                      a_init=0.02, a_final=1.0, n_steps=100, seed=3),
+                      a_init=0.02, a_final=1.0, n_steps=100, spacing=1, seed=3),
     # same per-particle and per-cell resolution as c3_pm2048, small enough for the FP64 oracle
     "c3_sibling256": dict(np_side=256, nm_side=256, nc_side=64, box=250.0, x_bytes=1, v_bytes=1,
                           omega_m=0.3, omega_l=0.7, h=0.7, sigma8=0.8, n_s=1.0,
-                          a_init=0.02, a_final=1.0, n_steps=100, seed=3),
+                          a_init=0.02, a_final=1.0, n_steps=100, spacing=1, seed=3),
 }
 
 

@@ -1,0 +1,50 @@
+"""Write the stored oracle results the GPU tests compare against (calls only oracle/ and synth).
+
+    python tests/golden/make_golden.py [c2_pm128] [c1_pm32]
+
+For each workload: Zel'dovich ICs from the oracle's Philox noise, the FP64 PM run to a = 1 on
+uncompressed particles, and the auto power spectrum of the final CIC density (shells 1..N_m/2).
+Output: tests/golden/<workload>_pk.json.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+from oracle import ic, pm, power  # noqa: E402
+from oracle.cosmology import Cosmology  # noqa: E402
+
+
+def run(name: str) -> dict:
+    cfg = synth.WORKLOADS[name]
+    cosmo = Cosmology(cfg["omega_m"], cfg["omega_l"], h=cfg["h"], sigma8=cfg["sigma8"], n_s=cfg["n_s"])
+    nm, npart = cfg["nm_side"], cfg["np_side"]
+    t0 = time.time()
+    x, p, _ = ic.zeldovich(npart, nm, cfg["box"], cosmo, cfg["a_init"], cfg["seed"])
+    k0, p0, n0 = power.power_spectrum(pm.density_contrast(pm.cic_deposit(x, nm), npart**3), cfg["box"])
+    r = pm.PMRun(x, p, nm, cosmo, cfg["a_init"], cfg["a_final"], cfg["n_steps"], cfg.get("spacing", 0))
+    while r.j < r.n_steps:
+        r.advance()
+        if r.j % 10 == 0:
+            print(f"{name}: step {r.j}/{r.n_steps} {time.time() - t0:.0f}s", flush=True)
+    delta = pm.density_contrast(pm.cic_deposit(r.x, nm), npart**3)
+    k, pk, nmodes = power.power_spectrum(delta, cfg["box"])
+    return dict(workload=name, config=cfg, a=cfg["a_final"], k=k.tolist(), pk=pk.tolist(), nmodes=nmodes.tolist(),
+                k_init=k0.tolist(), pk_init=p0.tolist(), source="oracle: ic.zeldovich + pm.PMRun + power.power_spectrum",
+                seconds=time.time() - t0)
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["c1_pm32", "c2_pm128"]
+    for name in names:
+        out = run(name)
+        with open(os.path.join(HERE, f"{name}_pk.json"), "w") as f:
+            json.dump(out, f, indent=1)
+        print(f"wrote {name}_pk.json in {out['seconds']:.0f}s")
