@@ -1,5 +1,6 @@
 // C ABI of libcube (declared in include/cube.h): simulation lifetime, schedule, and the calls of
 // the paper's main program (Fig. code): initial conditions, steps, checkpoint I/O, analysis.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -63,6 +64,19 @@ void build_tables(Sim& s) {
     if ((double)f < e) f = std::nextafterf(f, INFINITY);
     s.h_tedge[j + half - 1] = f;
   }
+  // bucket table: t = u / (1 + |u|) in (-1, 1) split into 4 (M + 1) buckets; each holds the code of
+  // the bucket's lower end. Only a starting guess: the kernels finish with exact edge comparisons.
+  s.nbucket = 4 * (m + 1);
+  std::vector<int16_t> lo(s.nbucket);
+  for (int b = 0; b < s.nbucket; ++b) {
+    const double t = -1.0 + 2.0 * b / s.nbucket;
+    const double u = b == 0 ? -INFINITY : t / (1.0 - std::fabs(t));
+    const int cnt = (int)(std::upper_bound(s.h_tedge.begin(), s.h_tedge.end(), u,
+                                           [](double a, float e) { return a < (double)e; }) - s.h_tedge.begin());
+    lo[b] = (int16_t)(cnt - half);
+  }
+  s.tbucket = static_cast<int16_t*>(s.dmalloc(sizeof(int16_t) * s.nbucket));
+  CUBE_HIP(hipMemcpy(s.tbucket, lo.data(), sizeof(int16_t) * s.nbucket, hipMemcpyHostToDevice));
   s.tdec = static_cast<float*>(s.dmalloc(sizeof(float) * m));
   s.tedge = static_cast<float*>(s.dmalloc(sizeof(float) * (m - 1)));
   CUBE_HIP(hipMemcpy(s.tdec, s.h_tdec.data(), sizeof(float) * m, hipMemcpyHostToDevice));

@@ -89,6 +89,8 @@ struct Sim {
   // codec tables (device)
   float* tdec = nullptr;   // M entries
   float* tedge = nullptr;  // M - 1 entries
+  int16_t* tbucket = nullptr;  // first guess of the velocity code per bucket of u / (1 + |u|)
+  int nbucket = 0;
   std::vector<float> h_tdec, h_tedge;
   int vm = 255;
 

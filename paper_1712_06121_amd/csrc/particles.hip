@@ -192,6 +192,8 @@ struct MoveArgs {
   float kf, df;
   const float* tdec;
   const float* tedge;
+  const int16_t* tbucket;
+  int nbucket;
   int vhalf;
   uint32_t* mig;
   const uint32_t* slot;
@@ -213,9 +215,27 @@ struct Moved {
   bool ok;
 };
 
-template <int NCHI, int NNU, int MODE>
-__device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* ph, int s, int64_t p, uint32_t li,
-                                               const TileGeom& g) {
+constexpr int DG = F + 2;  // precomputed-gradient tile side: fine cells -1 .. F of the tile
+
+// Gradient source: either the potential tile (4-point difference per corner) or the tile of
+// precomputed unnormalised gradients D = 8 (phi[i+1] - phi[i-1]) - (phi[i+2] - phi[i-2]).
+template <bool PRE>
+__device__ __forceinline__ float grad_at(const float* ph, const float* gd, int d, int x, int y, int z) {
+  // (x, y, z): fine cell relative to the tile origin, in -1 .. F
+  if constexpr (PRE) {
+    return gd[d * DG * DG * DG + ((z + 1) * DG + (y + 1)) * DG + (x + 1)];
+  } else {
+    const int e = d == 0 ? 1 : (d == 1 ? PH : PH * PH);
+    const int b = ((z + 3) * PH + (y + 3)) * PH + (x + 3);
+    const float aa = ph[b + e] - ph[b - e];
+    const float bb = ph[b + 2 * e] - ph[b - 2 * e];
+    return 8.0f * aa - bb;
+  }
+}
+
+template <int NCHI, int NNU, int MODE, bool PRE>
+__device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* ph, const float* gd, int s, int64_t p,
+                                               uint32_t li, const TileGeom& g) {
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
   constexpr int SH = 8 * NCHI - 1;
@@ -250,39 +270,29 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
       v[d] = a.vc[d * a.nc3 + c] + a.vs[c] * a.tdec[nuv + a.vhalf];
     }
     if constexpr (MODE == 0) {
-      // CIC corners and weights (exact dyadic), potential tile coordinates offset by the halo
+      // CIC corners (fine cells relative to the tile origin) and exact dyadic weights
       int i0[3];
       float w0[3], w1[3];
       const float wunit = (float)(1.0 / (double)(1 << SH));
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
-        i0[d] = (pl >> SH) + 3;
+        i0[d] = pl >> SH;
         const int f = pl & ((1 << SH) - 1);
         w0[d] = (float)((1 << SH) - f) * wunit;
         w1[d] = (float)f * wunit;
       }
-      const int sx = 1, sy = PH, sz = PH * PH;
-      const int strides[3] = {sx, sy, sz};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const int e = strides[d];
         float sacc[2];
 #pragma unroll
         for (int cz = 0; cz < 2; ++cz) {
           float racc[2];
 #pragma unroll
           for (int cy = 0; cy < 2; ++cy) {
-            const int b0 = (i0[2] + cz) * sz + (i0[1] + cy) * sy + i0[0];
-            float dg[2];
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-              const int b = b0 + cx;
-              const float aa = ph[b + e] - ph[b - e];
-              const float bb = ph[b + 2 * e] - ph[b - 2 * e];
-              dg[cx] = 8.0f * aa - bb;
-            }
-            racc[cy] = w0[0] * dg[0] + w1[0] * dg[1];
+            const float d0 = grad_at<PRE>(ph, gd, d, i0[0], i0[1] + cy, i0[2] + cz);
+            const float d1 = grad_at<PRE>(ph, gd, d, i0[0] + 1, i0[1] + cy, i0[2] + cz);
+            racc[cy] = w0[0] * d0 + w1[0] * d1;
           }
           sacc[cz] = w0[1] * racc[0] + w1[1] * racc[1];
         }
@@ -327,19 +337,38 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
   return m;
 }
 
-template <int NCHI, int MODE>
-__device__ __forceinline__ void load_potential(const MoveArgs& a, float* ph, const TileGeom& g) {
+// Potential tile (fine cells -3 .. F+2 of the tile, wrapped) and, with PRE, the unnormalised
+// 4-point gradient of every corner cell -1 .. F. The gradient uses the same IEEE operations as the
+// per-corner evaluation, so both paths give identical bits.
+template <int MODE, bool PRE, int NTH>
+__device__ __forceinline__ void load_potential(const MoveArgs& a, float* ph, float* gd, const TileGeom& g) {
   if constexpr (MODE == 0) {
+    // half-waves take rows (z, y); lanes take x
+    const int hw = threadIdx.x >> 5, x = threadIdx.x & 31;
     const int fx0 = g.cx0 * 4 - 3, fy0 = g.cy0 * 4 - 3, fz0 = g.cz0 * 4 - 3;
-    for (int i = threadIdx.x; i < PH * PH * PH; i += BLK) {
-      const int x = i % PH, y = (i / PH) % PH, z = i / (PH * PH);
-      const int gx = wrapi(fx0 + x, a.nm), gy = wrapi(fy0 + y, a.nm), gz = wrapi(fz0 + z, a.nm);
-      ph[i] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
+    const int gx = wrapi(fx0 + x, a.nm);
+    for (int r = hw; r < PH * PH; r += NTH / 32) {
+      if (x < PH) {
+        const int z = r / PH, y = r - z * PH;
+        const int gy = wrapi(fy0 + y, a.nm), gz = wrapi(fz0 + z, a.nm);
+        ph[r * PH + x] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
+      }
+    }
+    if constexpr (PRE) {
+      __syncthreads();
+      for (int r = hw; r < DG * DG; r += NTH / 32) {
+        if (x < DG) {
+          const int z = r / DG, y = r - z * DG;
+          const int i = r * DG + x;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) gd[d * DG * DG * DG + i] = grad_at<false>(ph, gd, d, x - 1, y - 1, z - 1);
+        }
+      }
     }
   }
 }
 
-// own cells of the tile: counts, starts and the exclusive prefix (one wave does the scan)
+// own cells of the tile: counts, starts and the exclusive prefix
 template <int MODE>
 __device__ __forceinline__ uint32_t own_cells(const MoveArgs& a, const TileGeom& g, uint32_t* pre, uint64_t* start,
                                               uint32_t* wsum) {
@@ -358,44 +387,108 @@ __device__ __forceinline__ uint32_t own_cells(const MoveArgs& a, const TileGeom&
   return block_exclusive_scan(cntv, pre, TC, wsum);
 }
 
-template <int NCHI, int NNU, int MODE>
-__global__ __launch_bounds__(BLK) void k_move_count(MoveArgs a) {
-  __shared__ float ph[MODE == 0 ? PH * PH * PH : 1];
+// Each wave owns a contiguous run of whole cells holding about total/W particles, so that a cell
+// is never shared between waves (ranks need no ordering across waves).
+__device__ __forceinline__ void wave_cells(const uint32_t* pre, uint32_t total, int wave, int nwaves, int& c0, int& c1) {
+  auto lower = [&](uint64_t t) {
+    int lo = 0, hi = TC;  // smallest s with pre[s] >= t
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((uint64_t)pre[mid] < t) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  c0 = wave == 0 ? 0 : lower((uint64_t)total * wave / nwaves);
+  c1 = wave == nwaves - 1 ? TC : lower((uint64_t)total * (wave + 1) / nwaves);
+}
+
+__device__ __forceinline__ int find_cell_in(const uint32_t* pre, int lo, int hi, uint32_t i) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int MODE, bool PRE>
+struct MoveLds {
+  static constexpr int kPh = MODE == 0 ? PH * PH * PH : 1;
+  static constexpr int kGd = (MODE == 0 && PRE) ? 3 * DG * DG * DG : 1;
+};
+
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
+__global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
+  __shared__ float ph[MoveLds<MODE, PRE>::kPh];
+  __shared__ float gd[MoveLds<MODE, PRE>::kGd];
   __shared__ uint32_t mcnt[TC * 27];
   __shared__ unsigned long long mom[RC * 4];
   __shared__ uint32_t pre[TC + 1];
   __shared__ uint64_t start[TC];
-  __shared__ uint32_t wsum[BLK / 64];
+  __shared__ uint32_t wsum[NTH / 64];
   const TileGeom g = tile_of(blockIdx.x, a.nt);
-  load_potential<NCHI, MODE>(a, ph, g);
-  for (int i = threadIdx.x; i < TC * 27; i += BLK) mcnt[i] = 0u;
-  for (int i = threadIdx.x; i < RC * 4; i += BLK) mom[i] = 0ull;
+  load_potential<MODE, PRE, NTH>(a, ph, gd, g);
+  for (int i = threadIdx.x; i < TC * 27; i += NTH) mcnt[i] = 0u;
+  for (int i = threadIdx.x; i < RC * 4; i += NTH) mom[i] = 0ull;
   const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
-  for (uint32_t i = threadIdx.x; i < total; i += BLK) {
-    const int s = find_cell(pre, TC, i);
-    const uint32_t li = i - pre[s];
-    const int64_t p = (int64_t)start[s] + li;
-    const Moved m = move_particle<NCHI, NNU, MODE>(a, ph, s, p, li, g);
-    const int dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
-    atomicAdd(&mcnt[s * 27 + dcode], 1u);
-    const int r = (s % T + 1 + m.k[0]) + RG * ((s / T) % T + 1 + m.k[1]) + RG * RG * (s / (T * T) + 1 + m.k[2]);
-    long long s2 = 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int c0, c1;
+  wave_cells(pre, total, wave, NTH / 64, c0, c1);
+  const uint32_t p0 = pre[c0], p1 = pre[c1];
+  for (uint32_t base = p0; base < p1; base += 64) {
+    const uint32_t i = base + lane;
+    const bool active = i < p1;  // active lanes form a prefix of the wave
+    int key = -1, r = 0;
+    long long q[4] = {0, 0, 0, 0};
+    if (active) {
+      const int s = find_cell_in(pre, c0, c1, i);
+      const uint32_t li = i - pre[s];
+      const int64_t p = (int64_t)start[s] + li;
+      const Moved m = move_particle<NCHI, NNU, MODE, PRE>(a, ph, gd, s, p, li, g);
+      const int dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
+      key = s * 27 + dcode;
+      r = (s % T + 1 + m.k[0]) + RG * ((s / T) % T + 1 + m.k[1]) + RG * RG * (s / (T * T) + 1 + m.k[2]);
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double vd = (double)m.v[d];
-      const long long t1 = __double2ll_rn(vd * 4294967296.0);
-      s2 += __double2ll_rn(vd * vd * 16777216.0);
-      atomicAdd(&mom[r * 4 + d], (unsigned long long)t1);
+      for (int d = 0; d < 3; ++d) {
+        const double vd = (double)m.v[d];
+        q[d] = __double2ll_rn(vd * 4294967296.0);
+        q[3] += __double2ll_rn(vd * vd * 16777216.0);
+      }
     }
-    atomicAdd(&mom[r * 4 + 3], (unsigned long long)s2);
+    // sum over runs of consecutive lanes with the same (cell, displacement): most particles stay
+    // in their cell, so one atomic per run replaces up to 64 conflicting ones
+    const int kprev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || kprev != key;
+    int st = head ? lane : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(st, o, 64);
+      if (lane >= o && y > st) st = y;
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(q[d], o, 64);
+        if (lane - o >= st) q[d] += y;
+      }
+    }
+    const int knext = __shfl_down(key, 1, 64);
+    const bool tail = lane == 63 || knext != key;
+    if (active && tail) {
+      atomicAdd(&mcnt[key], (uint32_t)(lane - st + 1));
+#pragma unroll
+      for (int d = 0; d < 4; ++d) atomicAdd(&mom[r * 4 + d], (unsigned long long)q[d]);
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < TC * 27; i += BLK) {
+  for (int i = threadIdx.x; i < TC * 27; i += NTH) {
     const int s = i / 27, d = i % 27;
     const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
     a.mig[d * a.nc3 + c] = mcnt[i];
   }
-  for (int i = threadIdx.x; i < RC * 4; i += BLK) {
+  for (int i = threadIdx.x; i < RC * 4; i += NTH) {
     const unsigned long long v = mom[i];
     if (v == 0ull) continue;
     const int r = i / 4, q = i % 4;
@@ -406,54 +499,64 @@ __global__ __launch_bounds__(BLK) void k_move_count(MoveArgs a) {
   }
 }
 
-template <int NNU>
-__device__ __forceinline__ int encode_nu(float u, const float* edges, int nedge, int vhalf) {
-  // number of edges <= u (upper bound), edges ascending
-  int lo = 0, hi = nedge;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (edges[mid] <= u) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo - vhalf;
+// Eq. (nu) by the edge table: the code nu with E[nu + h - 1] <= u < E[nu + h] (h = (M-1)/2), i.e.
+// -h + #{edges <= u}. A bucket table over t = u / (1 + |u|) gives a starting code; the two loops
+// then settle on the exact code whatever the start, so the result equals a full search.
+__device__ __forceinline__ int encode_nu(float u, const float* edges, const int16_t* bucket, int nbucket, int vhalf) {
+  const float t = u / (1.0f + fabsf(u));
+  int b = (int)((t + 1.0f) * (0.5f * (float)nbucket));
+  b = b < 0 ? 0 : (b > nbucket - 1 ? nbucket - 1 : b);
+  int nu = bucket[b];
+  while (nu < vhalf && u >= edges[nu + vhalf]) ++nu;
+  while (nu > -vhalf && u < edges[nu + vhalf - 1]) --nu;
+  return nu;
 }
 
-template <int NCHI, int NNU, int MODE>
-__global__ __launch_bounds__(BLK) void k_move_scatter(MoveArgs a) {
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
+__global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
-  __shared__ float ph[MODE == 0 ? PH * PH * PH : 1];
+  __shared__ float ph[MoveLds<MODE, PRE>::kPh];
+  __shared__ float gd[MoveLds<MODE, PRE>::kGd];
   __shared__ uint32_t grp[TC * 27];
   __shared__ uint32_t pre[TC + 1];
   __shared__ uint64_t start[TC];
-  __shared__ uint32_t wsum[BLK / 64];
+  __shared__ uint32_t wsum[NTH / 64];
   __shared__ float edges_lds[NNU == 1 ? 254 : 1];
+  __shared__ int16_t bucket_lds[NNU == 1 ? 1024 : 1];
   const TileGeom g = tile_of(blockIdx.x, a.nt);
-  load_potential<NCHI, MODE>(a, ph, g);
-  for (int i = threadIdx.x; i < TC * 27; i += BLK) grp[i] = 0u;
+  load_potential<MODE, PRE, NTH>(a, ph, gd, g);
+  for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
   const int nedge = 2 * a.vhalf;
-  if constexpr (NNU == 1)
-    for (int i = threadIdx.x; i < nedge; i += BLK) edges_lds[i] = a.tedge[i];
+  if constexpr (NNU == 1) {
+    for (int i = threadIdx.x; i < nedge; i += NTH) edges_lds[i] = a.tedge[i];
+    for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = a.tbucket[i];
+  }
   const float* edges = (NNU == 1) ? edges_lds : a.tedge;
+  const int16_t* bucket = (NNU == 1) ? bucket_lds : a.tbucket;
   const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
   CT* chi_n = static_cast<CT*>(a.chi_n);
   NT* nu_n = static_cast<NT*>(a.nu_n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  for (uint32_t base_i = 0; base_i < total; base_i += BLK) {
-    const uint32_t i = base_i + threadIdx.x;
-    const bool active = i < total;
+  int c0, c1;
+  wave_cells(pre, total, wave, NTH / 64, c0, c1);
+  const uint32_t p0 = pre[c0], p1 = pre[c1];
+  // particles of this wave's cells in storage order; the running count per (source cell,
+  // displacement) gives every particle its rank inside the new cell
+  for (uint32_t base = p0; base < p1; base += 64) {
+    const uint32_t i = base + lane;
+    const bool active = i < p1;
     Moved m{};
-    int s = 0, key = 0, dcode = 0;
+    int s = c0, key = 0, dcode = 0;
     if (active) {
-      s = find_cell(pre, TC, i);
+      s = find_cell_in(pre, c0, c1, i);
       const uint32_t li = i - pre[s];
       const int64_t p = (int64_t)start[s] + li;
-      m = move_particle<NCHI, NNU, MODE>(a, ph, s, p, li, g);
+      m = move_particle<NCHI, NNU, MODE, PRE>(a, ph, gd, s, p, li, g);
       dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
       key = s * 27 + dcode;
     }
-    // peers with the same (source cell, displacement) in this wave
     unsigned long long peers = __ballot(active);
 #pragma unroll
     for (int b = 0; b < 11; ++b) {
@@ -462,33 +565,29 @@ __global__ __launch_bounds__(BLK) void k_move_scatter(MoveArgs a) {
       peers &= bit ? bb : ~bb;
     }
     const int rin = __popcll(peers & lt);
-    const int leader = __ffsll((long long)peers) - 1;
+    const int leader = active ? __ffsll((long long)peers) - 1 : lane;
     uint32_t gbase = 0;
-    // waves take their turn in order so that ranks follow storage order
-    for (int w = 0; w < BLK / 64; ++w) {
-      if (w == wave && active && rin == 0) {
-        gbase = grp[key];
-        grp[key] = gbase + (uint32_t)__popcll(peers);
-      }
-      __syncthreads();
+    if (active && rin == 0) {
+      gbase = grp[key];
+      grp[key] = gbase + (uint32_t)__popcll(peers);
     }
-    gbase = (uint32_t)__shfl((int)gbase, leader < 0 ? 0 : leader, 64);
+    gbase = (uint32_t)__shfl((int)gbase, leader, 64);
     if (active) {
       const int ox = s % T, oy = (s / T) % T, oz = s / (T * T);
       const int nx = wrapi(g.cx0 + ox + m.k[0], a.nc), ny = wrapi(g.cy0 + oy + m.k[1], a.nc);
       const int nz = wrapi(g.cz0 + oz + m.k[2], a.nc);
       const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
       const uint64_t dst = a.off_n[cn] + a.slot[(int64_t)(26 - dcode) * a.nc3 + cn] + gbase + (uint32_t)rin;
-      if (dst >= (uint64_t)a.cap) {
-        set_flag(a.flags, FLAG_COUNT);
-        continue;
-      }
-      const float inv = a.vinv[cn];
+      if (dst < (uint64_t)a.cap) {
+        const float inv = a.vinv[cn];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float u = (m.v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
-        nu_n[d * a.cap + dst] = (NT)encode_nu<NNU>(u, edges, nedge, a.vhalf);
-        chi_n[d * a.cap + dst] = (CT)m.chi[d];
+        for (int d = 0; d < 3; ++d) {
+          const float u = (m.v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
+          nu_n[d * a.cap + dst] = (NT)encode_nu(u, edges, bucket, a.nbucket, a.vhalf);
+          chi_n[d * a.cap + dst] = (CT)m.chi[d];
+        }
+      } else {
+        set_flag(a.flags, FLAG_COUNT);
       }
     }
   }
@@ -710,7 +809,8 @@ __global__ void k_load_codes(LoadArgs a) {
 template <int NCHI, int NNU>
 __global__ void k_load_encode(const uint32_t* key_sorted, const uint32_t* idx_sorted, const uint16_t* chi_tmp,
                               const float* v_tmp, int64_t n, void* chi_out, void* nu_out, int64_t cap,
-                              const float* vc, const float* vinv, int64_t nc3, const float* edges, int vhalf) {
+                              const float* vc, const float* vinv, int64_t nc3, const float* edges,
+                              const int16_t* bucket, int nbucket, int vhalf) {
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -723,7 +823,7 @@ __global__ void k_load_encode(const uint32_t* key_sorted, const uint32_t* idx_so
   for (int d = 0; d < 3; ++d) {
     co[d * cap + j] = (CT)chi_tmp[d * n + src];
     const float u = (v_tmp[d * n + src] - vc[d * nc3 + c]) * inv;
-    no[d * cap + j] = (NT)encode_nu<NNU>(u, edges, 2 * vhalf, vhalf);
+    no[d * cap + j] = (NT)encode_nu(u, edges, bucket, nbucket, vhalf);
   }
 }
 
@@ -852,6 +952,8 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   a.df = dfac;
   a.tdec = s.tdec;
   a.tedge = s.tedge;
+  a.tbucket = s.tbucket;
+  a.nbucket = s.nbucket;
   a.vhalf = (s.vm - 1) / 2;
   a.mig = s.mig;
   a.slot = s.slot;
@@ -868,17 +970,21 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
     a.lunit = (float)(2.0 / (double)a.q);
   }
   const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
-#define CUBE_COUNT(X, V)                                                      \
-  do {                                                                        \
-    if (mode == 0) k_move_count<X, V, 0><<<grid, BLK, 0, st>>>(a);            \
-    else if (mode == 1) k_move_count<X, V, 1><<<grid, BLK, 0, st>>>(a);       \
-    else k_move_count<X, V, 2><<<grid, BLK, 0, st>>>(a);                      \
+  // precomputed gradient tile when particles are at least half as many as fine cells
+  const bool pre = mode == 0 && 2 * s.n >= (int64_t)s.nm * s.nm * s.nm;
+#define CUBE_COUNT(X, V)                                                                        \
+  do {                                                                                          \
+    if (mode == 0 && pre) k_move_count<X, V, 0, true, 1024><<<grid, 1024, 0, st>>>(a);           \
+    else if (mode == 0) k_move_count<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);              \
+    else if (mode == 1) k_move_count<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);              \
+    else k_move_count<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                             \
   } while (0)
-#define CUBE_SCATTER(X, V)                                                    \
-  do {                                                                        \
-    if (mode == 0) k_move_scatter<X, V, 0><<<grid, BLK, 0, st>>>(a);          \
-    else if (mode == 1) k_move_scatter<X, V, 1><<<grid, BLK, 0, st>>>(a);     \
-    else k_move_scatter<X, V, 2><<<grid, BLK, 0, st>>>(a);                    \
+#define CUBE_SCATTER(X, V)                                                                      \
+  do {                                                                                          \
+    if (mode == 0 && pre) k_move_scatter<X, V, 0, true, 1024><<<grid, 1024, 0, st>>>(a);         \
+    else if (mode == 0) k_move_scatter<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);            \
+    else if (mode == 1) k_move_scatter<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);            \
+    else k_move_scatter<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                           \
   } while (0)
   if (evs) CUBE_HIP(hipEventRecord(evs[0], st));
   CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_COUNT);
@@ -932,7 +1038,7 @@ void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, h
 #define CUBE_ENC(X, V)                                                                                       \
   k_load_encode<X, V><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(key2, idx2, chi_tmp, v_tmp, n, s.chi[nxt], \
                                                                    s.nu[nxt], s.capacity, s.vc[nxt], s.vinv, \
-                                                                   s.nc3, s.tedge, (s.vm - 1) / 2)
+                                                                   s.nc3, s.tedge, s.tbucket, s.nbucket, (s.vm - 1) / 2)
   if (n > 0) {
     CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_ENC);
     CUBE_HIP(hipGetLastError());

@@ -21,6 +21,11 @@ WORKLOADS = {
     "c3_pm2048": dict(np_side=2048, nm_side=2048, nc_side=512, box=2000.0, x_bytes=1, v_bytes=1,
                       omega_m=0.3, omega_l=0.7, h=0.7, sigma8=0.8, n_s=1.0,
                       a_init=0.02, a_final=1.0, n_steps=100, spacing=1, seed=3),
+    # c3_pm2048's particle and cell resolution (64 particles per coarse cell) on a smaller box,
+    # for profiling and kernel tuning
+    "c3_density512": dict(np_side=512, nm_side=512, nc_side=128, box=500.0, x_bytes=1, v_bytes=1,
+                          omega_m=0.3, omega_l=0.7, h=0.7, sigma8=0.8, n_s=1.0,
+                          a_init=0.02, a_final=1.0, n_steps=100, spacing=1, seed=3),
     # same per-particle and per-cell resolution as c3_pm2048, small enough for the FP64 oracle
     "c3_sibling256": dict(np_side=256, nm_side=256, nc_side=64, box=250.0, x_bytes=1, v_bytes=1,
                           omega_m=0.3, omega_l=0.7, h=0.7, sigma8=0.8, n_s=1.0,

@@ -107,6 +107,10 @@ MOVE_CASES = [
     (1, 2, 0, 32, 9000, 1.0),
     (2, 2, 1, 64, 25000, 0.5),
     (1, 1, 1, 128, 150000, 1.5),
+    # at least half as many particles as fine cells: the gradient tile is precomputed in LDS
+    (1, 1, 1, 32, 20000, 1.0),
+    (2, 1, 0, 64, 160000, 1.0),
+    (1, 1, 1, 64, 300000, 0.7),
 ]
 
 
