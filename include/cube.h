@@ -88,7 +88,8 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
 /* Release every resource of the simulation (the paper's `finalize`). NULL is a no-op. */
 void cube_destroy(cube_sim* sim);
 
-/* Text of the last error of `sim` ("" if none). Owned by the simulation. */
+/* Text of the last error of `sim` ("" if none), owned by the simulation. With sim == NULL: the
+ * text of the last failed cube_create on the calling thread. */
 const char* cube_last_error(const cube_sim* sim);
 
 /* Zel'dovich initial conditions at a_init (Sec. 2.3.2, Fig. ic): Philox white noise on the

@@ -68,6 +68,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libcube.so not found at {path}: build it with `python -m paper_1712_06121_amd.build`")
+    # PyTorch bundles its own HIP runtime with the same soname as the system one libcube links
+    # against. Import it first so the process holds a single runtime (the one that owns the
+    # streams and device memory PyTorch hands to the library).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     sim_p = c_void_p
     lib.cube_create.argtypes = [POINTER(CubeParams), c_void_p, POINTER(CubeAllocator), POINTER(c_void_p)]
@@ -151,7 +158,7 @@ class Sim:
         self._h = c_void_p()
         rc = self._lib.cube_create(byref(self.params), stream, alloc_p, byref(self._h))
         if rc != CUBE_OK:
-            raise CubeError(rc, "cube_create failed")
+            raise CubeError(rc, "cube_create: " + self._lib.cube_last_error(None).decode())
 
     # ---- helpers -----------------------------------------------------------------------------
     def _check(self, rc: int) -> int:

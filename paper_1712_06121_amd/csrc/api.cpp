@@ -12,6 +12,10 @@ struct cube_sim {
   cube::Sim s;
 };
 
+namespace {
+thread_local std::string g_create_error;  // text of the last failed cube_create on this thread
+}
+
 namespace cube {
 
 void* Sim::dmalloc(size_t bytes) {
@@ -220,7 +224,7 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
     if (!cube::pow2(p.nm_side) || p.nm_side < 32 || p.nm_side > 2048)
       throw Error{CUBE_E_INVALID, "nm_side must be a power of two in [32, 2048]"};
     if (p.nc_side * 4 != p.nm_side) throw Error{CUBE_E_INVALID, "nc_side must be nm_side / 4"};
-    if (p.nc_side % 4 != 0) throw Error{CUBE_E_INVALID, "nc_side must be a multiple of 4"};
+    if (p.nc_side % 8 != 0) throw Error{CUBE_E_INVALID, "nc_side must be a multiple of 8"};
     if (!cube::pow2(p.np_side) || p.np_side < 32 || p.np_side > 2048 || p.np_side % p.nc_side != 0)
       throw Error{CUBE_E_INVALID, "np_side must be a power of two in [32, 2048] and a multiple of nc_side"};
     if (p.x_bytes < 1 || p.x_bytes > 2 || p.v_bytes < 1 || p.v_bytes > 2)
@@ -280,12 +284,11 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
     for (auto& e : s.ev) CUBE_HIP(hipEventCreate(&e));
     s.a_now = p.a_init;
   } catch (const Error& e) {
-    const int code = e.code;
-    std::string msg = e.msg;
+    g_create_error = e.msg;
     cube_destroy(sim);
-    (void)msg;
-    return code;
-  } catch (...) {
+    return e.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
     cube_destroy(sim);
     return CUBE_E_NOMEM;
   }
@@ -305,7 +308,7 @@ void cube_destroy(cube_sim* sim) {
   delete sim;
 }
 
-const char* cube_last_error(const cube_sim* sim) { return sim ? sim->s.last_error.c_str() : "null simulation"; }
+const char* cube_last_error(const cube_sim* sim) { return sim ? sim->s.last_error.c_str() : g_create_error.c_str(); }
 
 int cube_init_ic(cube_sim* sim) {
   if (!sim) return CUBE_E_INVALID;

@@ -161,11 +161,21 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
   __shared__ float2 lds[NL * H];
   const int64_t row0 = (int64_t)blockIdx.x * NL;
   constexpr int F4 = N / 4;
-  for (int i = threadIdx.x; i < NL * F4; i += BLOCK) {
+  constexpr int LPT = NL * F4 / BLOCK;
+  static_assert(NL * F4 % BLOCK == 0, "block must divide the rows");
+  float4 stage[LPT];
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = threadIdx.x + k * BLOCK;
     const int l = i / F4, c = i % F4;
-    const float4 q = *reinterpret_cast<const float4*>(data + (row0 + l) * pitch_f + 4 * c);
-    lds[l * H + 2 * c] = make_float2(q.x, q.y);
-    lds[l * H + 2 * c + 1] = make_float2(q.z, q.w);
+    stage[k] = *reinterpret_cast<const float4*>(data + (row0 + l) * pitch_f + 4 * c);
+  }
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = threadIdx.x + k * BLOCK;
+    const int l = i / F4, c = i % F4;
+    lds[l * H + 2 * c] = make_float2(stage[k].x, stage[k].y);
+    lds[l * H + 2 * c + 1] = make_float2(stage[k].z, stage[k].w);
   }
   __syncthreads();
   fft_lds<H, 1, NL, H, 1, BLOCK, -1, 2>(lds, tw);
@@ -191,9 +201,20 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
   constexpr int LS = H + 1;
   __shared__ float2 lds[NL * LS];
   const int64_t row0 = (int64_t)blockIdx.x * NL;
-  for (int i = threadIdx.x; i < NL * LS; i += BLOCK) {
-    const int l = i / LS, c = i % LS;
-    lds[l * LS + c] = reinterpret_cast<const float2*>(data + (row0 + l) * pitch_f)[c];
+  constexpr int LPT = (NL * LS + BLOCK - 1) / BLOCK;
+  float2 stage[LPT];
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = threadIdx.x + k * BLOCK;
+    if (i < NL * LS) {
+      const int l = i / LS, c = i % LS;
+      stage[k] = reinterpret_cast<const float2*>(data + (row0 + l) * pitch_f)[c];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = threadIdx.x + k * BLOCK;
+    if (i < NL * LS) lds[i] = stage[k];
   }
   __syncthreads();
   constexpr int NP = H / 2 + 1;
@@ -245,11 +266,22 @@ __global__ __launch_bounds__(ColCfg<N>::BLOCK) void k_fft_col(const float2* __re
   const int cb = blockIdx.x, o = blockIdx.y;
   const int64_t base = (int64_t)o * ostride + (int64_t)cb * BX;
   constexpr int Q = BX / 2;
-  for (int i = threadIdx.x; i < N * Q; i += BLOCK) {
+  // every load of the block in flight at once (registers), then into LDS
+  constexpr int LPT = N * Q / BLOCK;
+  static_assert(N * Q % BLOCK == 0, "block must divide the column block");
+  float4 stage[LPT];
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = threadIdx.x + k * BLOCK;
     const int t = i / Q, c = i % Q;
-    const float4 q = *reinterpret_cast<const float4*>(src + base + (int64_t)t * tstride + 2 * c);
-    lds[t * BX + 2 * c] = make_float2(q.x, q.y);
-    lds[t * BX + 2 * c + 1] = make_float2(q.z, q.w);
+    stage[k] = *reinterpret_cast<const float4*>(src + base + (int64_t)t * tstride + 2 * c);
+  }
+#pragma unroll
+  for (int k = 0; k < LPT; ++k) {
+    const int i = threadIdx.x + k * BLOCK;
+    const int t = i / Q, c = i % Q;
+    lds[t * BX + 2 * c] = make_float2(stage[k].x, stage[k].y);
+    lds[t * BX + 2 * c + 1] = make_float2(stage[k].z, stage[k].w);
   }
   __syncthreads();
   if constexpr (MODE == COL_FWD || MODE == COL_GREEN || MODE == COL_POWER)

@@ -100,71 +100,94 @@ struct DepArgs {
   float* mesh;
   int64_t pitch_f;
   int nm, nc, nt;
+  int zc;  // coarse layers per z chunk
   double inv_mean;
 };
 
+constexpr int DTX = 8;            // coarse cells per column side
+constexpr int DF = 4 * DTX;       // fine cells per column side
+constexpr int DR = DTX + 2;       // source cells per side (column + ring)
+constexpr int DRC = DR * DR;      // source cells per coarse layer
+constexpr int NSLOT = 6;          // fine planes a coarse layer can touch
+
+__device__ __forceinline__ int slot_of(int p) { return ((p % NSLOT) + NSLOT) % NSLOT; }
+
+// Streaming gather: the workgroup owns a DF x DF column of fine cells over the fine planes of
+// coarse layers [cz0, cz1). It walks the source coarse layers cz0-1 .. cz1 in order, each time
+// reading the particles of the DR x DR cells (column + ring), and adds exact integer CIC weights
+// to a rolling set of NSLOT fine planes in LDS. After layer sz, planes up to 4 sz + 2 receive no
+// more mass: they are converted once to FP32 delta, written, and their slots reused.
 template <int NCHI>
 __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   using CT = chi_t<NCHI>;
   constexpr int SH = 8 * NCHI - 1;
-  __shared__ unsigned long long rho[F * F * F];
-  __shared__ uint32_t pre[SRC + 1];
-  __shared__ uint64_t start[SRC];
+  __shared__ unsigned long long rho[NSLOT * DF * DF];
+  __shared__ uint32_t pre[DRC + 1];
+  __shared__ uint64_t start[DRC];
   __shared__ uint32_t wsum[BLK / 64];
-  const TileGeom g = tile_of(blockIdx.x, a.nt);
-  for (int i = threadIdx.x; i < F * F * F; i += BLK) rho[i] = 0ull;
-  uint32_t cntv = 0;
-  if (threadIdx.x < SRC) {
-    const int s = threadIdx.x;
-    const int sx = s % RG - 1, sy = (s / RG) % RG - 1, sz = s / (RG * RG) - 1;
-    const int gx = wrapi(g.cx0 + sx, a.nc), gy = wrapi(g.cy0 + sy, a.nc), gz = wrapi(g.cz0 + sz, a.nc);
-    const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
-    cntv = a.cnt[c];
-    start[s] = a.off[c];
-  }
-  const uint32_t total = block_exclusive_scan(cntv, pre, SRC, wsum);
+  const int cx0 = (blockIdx.x % a.nt) * DTX, cy0 = (blockIdx.x / a.nt) * DTX;
+  const int cz0 = blockIdx.y * a.zc;
+  const int cz1 = min(cz0 + a.zc, a.nc);
+  const int pz0 = 4 * cz0, pz1 = 4 * cz1;  // owned fine planes [pz0, pz1)
+  for (int i = threadIdx.x; i < NSLOT * DF * DF; i += BLK) rho[i] = 0ull;
   const CT* cx = static_cast<const CT*>(a.chi);
   const CT* cy = cx + a.cap;
   const CT* cz = cy + a.cap;
-  for (uint32_t i = threadIdx.x; i < total; i += BLK) {
-    const int s = find_cell(pre, SRC, i);
-    const int64_t p = (int64_t)start[s] + (i - pre[s]);
-    const int sl[3] = {s % RG - 1, (s / RG) % RG - 1, s / (RG * RG) - 1};
-    const int ch[3] = {(int)cx[p], (int)cy[p], (int)cz[p]};
-    int i0[3], w1[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int pl = sl[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
-      i0[d] = pl >> SH;
-      w1[d] = pl & ((1 << SH) - 1);
+  for (int sz = cz0 - 1; sz <= cz1; ++sz) {
+    uint32_t cntv = 0;
+    if (threadIdx.x < DRC) {
+      const int sx = threadIdx.x % DR - 1, sy = threadIdx.x / DR - 1;
+      const int64_t c = wrapi(cx0 + sx, a.nc) + (int64_t)a.nc * (wrapi(cy0 + sy, a.nc) + (int64_t)a.nc * wrapi(sz, a.nc));
+      cntv = a.cnt[c];
+      start[threadIdx.x] = a.off[c];
     }
+    const uint32_t total = block_exclusive_scan(cntv, pre, DRC, wsum);
+    for (uint32_t i = threadIdx.x; i < total; i += BLK) {
+      const int s = find_cell(pre, DRC, i);
+      const int64_t p = (int64_t)start[s] + (i - pre[s]);
+      const int sl[3] = {s % DR - 1, s / DR - 1, sz};
+      const int ch[3] = {(int)cx[p], (int)cy[p], (int)cz[p]};
+      int i0[3], w1[3];
 #pragma unroll
-    for (int dz = 0; dz < 2; ++dz) {
-      const int z = i0[2] + dz;
-      if (z < 0 || z >= F) continue;
-      const unsigned long long wz = dz ? (unsigned long long)w1[2] : (unsigned long long)((1 << SH) - w1[2]);
+      for (int d = 0; d < 3; ++d) {
+        const int pl = sl[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
+        i0[d] = pl >> SH;
+        w1[d] = pl & ((1 << SH) - 1);
+      }
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy) {
-        const int y = i0[1] + dy;
-        if (y < 0 || y >= F) continue;
-        const unsigned long long wy = dy ? (unsigned long long)w1[1] : (unsigned long long)((1 << SH) - w1[1]);
+      for (int dz = 0; dz < 2; ++dz) {
+        const int pz = i0[2] + dz;
+        if (pz < pz0 || pz >= pz1) continue;
+        const int sb = slot_of(pz) * DF * DF;
+        const unsigned long long wz = dz ? (unsigned long long)w1[2] : (unsigned long long)((1 << SH) - w1[2]);
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const int x = i0[0] + dx;
-          if (x < 0 || x >= F) continue;
-          const unsigned long long wx = dx ? (unsigned long long)w1[0] : (unsigned long long)((1 << SH) - w1[0]);
-          atomicAdd(&rho[(z * F + y) * F + x], wz * wy * wx);
+        for (int dy = 0; dy < 2; ++dy) {
+          const int y = i0[1] + dy;
+          if (y < 0 || y >= DF) continue;
+          const unsigned long long wy = dy ? (unsigned long long)w1[1] : (unsigned long long)((1 << SH) - w1[1]);
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const int x = i0[0] + dx;
+            if (x < 0 || x >= DF) continue;
+            const unsigned long long wx = dx ? (unsigned long long)w1[0] : (unsigned long long)((1 << SH) - w1[0]);
+            atomicAdd(&rho[sb + y * DF + x], wz * wy * wx);
+          }
         }
       }
     }
-  }
-  __syncthreads();
-  const int fx0 = g.cx0 * 4, fy0 = g.cy0 * 4, fz0 = g.cz0 * 4;
-  for (int i = threadIdx.x; i < F * F * F; i += BLK) {
-    const int x = i % F, y = (i / F) % F, z = i / (F * F);
-    const double r = (double)rho[i];
-    const float dlt = (float)(r * a.inv_mean - 1.0);
-    a.mesh[((int64_t)(fz0 + z) * a.nm + (fy0 + y)) * a.pitch_f + (fx0 + x)] = dlt;
+    __syncthreads();
+    // planes completed by this layer
+    const int f0 = max(4 * sz - 1, pz0), f1 = min(4 * sz + 2, pz1 - 1);
+    const int nplanes = f1 - f0 + 1;
+    for (int i = threadIdx.x; i < nplanes * DF * DF; i += BLK) {
+      const int pz = f0 + i / (DF * DF), e = i % (DF * DF);
+      const int y = e / DF, x = e - y * DF;
+      const int idx = slot_of(pz) * DF * DF + e;
+      const double r = (double)rho[idx];
+      rho[idx] = 0ull;
+      a.mesh[((int64_t)pz * a.nm + (4 * cy0 + y)) * a.pitch_f + (4 * cx0 + x)] = (float)(r * a.inv_mean - 1.0);
+    }
+    __syncthreads();
   }
 }
 
@@ -347,12 +370,22 @@ __device__ __forceinline__ void load_potential(const MoveArgs& a, float* ph, flo
     const int hw = threadIdx.x >> 5, x = threadIdx.x & 31;
     const int fx0 = g.cx0 * 4 - 3, fy0 = g.cy0 * 4 - 3, fz0 = g.cz0 * 4 - 3;
     const int gx = wrapi(fx0 + x, a.nm);
-    for (int r = hw; r < PH * PH; r += NTH / 32) {
-      if (x < PH) {
+    // all loads of the tile in flight at once, then into LDS
+    constexpr int NR = (PH * PH + NTH / 32 - 1) / (NTH / 32);
+    float stage[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int r = hw + k * (NTH / 32);
+      if (x < PH && r < PH * PH) {
         const int z = r / PH, y = r - z * PH;
         const int gy = wrapi(fy0 + y, a.nm), gz = wrapi(fz0 + z, a.nm);
-        ph[r * PH + x] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
+        stage[k] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
       }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int r = hw + k * (NTH / 32);
+      if (x < PH && r < PH * PH) ph[r * PH + x] = stage[k];
     }
     if constexpr (PRE) {
       __syncthreads();
@@ -589,6 +622,253 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
       } else {
         set_flag(a.flags, FLAG_COUNT);
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Dense move passes (at least half as many particles as fine cells): one coarse cell per wave at
+// a time, so the cell's offset, mean velocity and scale are wave-uniform; the stayers of a cell
+// (the large majority) are summed with one cross-lane reduction; particles of a cell are visited
+// in storage order by a single wave, which makes the running rank per displacement exact.
+// ---------------------------------------------------------------------------------------------
+template <unsigned CTRL>
+__device__ __forceinline__ unsigned long long dpp_add_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xF, 0xF, false);
+  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xF, 0xF, false);
+  return v + (((unsigned long long)h2 << 32) | l2);
+}
+
+// sum over the 64 lanes (every lane active), returned to all lanes
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  v = dpp_add_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add_u64<0x141>(v);  // row_half_mirror
+  v = dpp_add_u64<0x140>(v);  // row_mirror: every lane holds its 16-lane row sum
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  unsigned long long t = 0;
+#pragma unroll
+  for (int r = 15; r < 64; r += 16)
+    t += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, r) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
+  return t;
+}
+
+template <int NCHI, int NNU, bool SCATTER>
+__global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
+  using CT = chi_t<NCHI>;
+  using NT = nu_t<NNU>;
+  constexpr int NTH = 1024;
+  constexpr int SH = 8 * NCHI - 1;
+  __shared__ float ph[PH * PH * PH];
+  __shared__ float gd[3 * DG * DG * DG];
+  __shared__ uint32_t grp[TC * 27];              // count pass: per (cell, displacement) counts; scatter: ranks
+  __shared__ unsigned long long mom[SCATTER ? 1 : RC * 4];
+  __shared__ uint32_t pre[TC + 1];
+  __shared__ uint64_t start[TC];
+  __shared__ uint32_t wsum[NTH / 64];
+  __shared__ float tdec_lds[NNU == 1 ? 255 : 1];
+  __shared__ float edges_lds[(SCATTER && NNU == 1) ? 254 : 1];
+  __shared__ int16_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];
+  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  load_potential<0, true, NTH>(a, ph, gd, g);
+  for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
+  if constexpr (!SCATTER)
+    for (int i = threadIdx.x; i < RC * 4; i += NTH) mom[i] = 0ull;
+  if constexpr (NNU == 1) {
+    for (int i = threadIdx.x; i < 255; i += NTH) tdec_lds[i] = a.tdec[i];
+    if constexpr (SCATTER) {
+      for (int i = threadIdx.x; i < 254; i += NTH) edges_lds[i] = a.tedge[i];
+      for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = a.tbucket[i];
+    }
+  }
+  const float* tdec = NNU == 1 ? tdec_lds : a.tdec;
+  const float* edges = NNU == 1 ? edges_lds : a.tedge;
+  const int16_t* bucket = NNU == 1 ? bucket_lds : a.tbucket;
+  __shared__ uint32_t next_cell;
+  if (threadIdx.x == 0) next_cell = NTH / 64;
+  own_cells<0>(a, g, pre, start, wsum);  // ends with a barrier
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  const float unit = (float)(1.0 / (double)(1 << SH));
+  CT* chi_n = static_cast<CT*>(a.chi_n);
+  NT* nu_n = static_cast<NT*>(a.nu_n);
+  // cells are handed out one at a time, so a wave that drew a crowded cell does not hold up the rest
+  for (int s = wave; s < TC;) {
+    const int o0 = s % T, o1 = (s / T) % T, o2 = s / (T * T);
+    const int64_t c = (g.cx0 + o0) + (int64_t)a.nc * ((g.cy0 + o1) + (int64_t)a.nc * (g.cz0 + o2));
+    const uint32_t n = pre[s + 1] - pre[s];
+    const uint64_t base = start[s];
+    const CT* chx = static_cast<const CT*>(a.chi) + base;
+    const NT* nux = static_cast<const NT*>(a.nu) + base;
+    const float vcx = a.vc[c], vcy = a.vc[a.nc3 + c], vcz = a.vc[2 * a.nc3 + c], vsc = a.vs[c];
+    const int r_stay = (o0 + 1) + RG * ((o1 + 1) + RG * (o2 + 1));
+    for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+      const uint32_t j = j0 + lane;
+      const bool active = j < n;
+      float v[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
+      int ch[3] = {0, 0, 0};
+      if (active) {
+        const float vcv[3] = {vcx, vcy, vcz};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          ch[d] = (int)chx[d * a.cap + j];
+          int nuv = (int)nux[d * a.cap + j];
+          nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
+          l[d] = (float)(2 * ch[d] + 1) * unit;
+          v[d] = vcv[d] + vsc * tdec[nuv + a.vhalf];
+        }
+        // CIC corners relative to the tile, exact dyadic weights, interpolated gradient
+        const int o[3] = {o0, o1, o2};
+        int i0[3];
+        float w0[3], w1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
+          i0[d] = pl >> SH;
+          const int f = pl & ((1 << SH) - 1);
+          w0[d] = (float)((1 << SH) - f) * unit;
+          w1[d] = (float)f * unit;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          float sacc[2];
+#pragma unroll
+          for (int cz = 0; cz < 2; ++cz) {
+            float racc[2];
+#pragma unroll
+            for (int cy = 0; cy < 2; ++cy) {
+              const float d0 = grad_at<true>(ph, gd, d, i0[0], i0[1] + cy, i0[2] + cz);
+              const float d1 = grad_at<true>(ph, gd, d, i0[0] + 1, i0[1] + cy, i0[2] + cz);
+              racc[cy] = w0[0] * d0 + w1[0] * d1;
+            }
+            sacc[cz] = w0[1] * racc[0] + w1[1] * racc[1];
+          }
+          const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
+          v[d] = v[d] + t * a.kf;
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
+      }
+      // new cell, codes, flags (same rules as the generic path)
+      int k[3], cq[3];
+      bool ok = true;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float ln = l[d];
+        int kk = 0;
+        float lw = ln;
+        if (!(ln == ln) || fabsf(ln) == INFINITY || !(v[d] == v[d]) || fabsf(v[d]) == INFINITY) {
+          set_flag(a.flags, FLAG_NONFINITE);
+          ok = false;
+          lw = 0.0f;
+        } else if (ln < -4.0f || ln >= 8.0f) {
+          set_flag(a.flags, FLAG_CFL);
+          ok = false;
+          lw = 0.0f;
+        } else if (ln < 0.0f) {
+          kk = -1;
+          lw = ln + 4.0f;
+        } else if (ln >= 4.0f) {
+          kk = 1;
+          lw = ln - 4.0f;
+        }
+        if (fabsf(v[d]) >= 32768.0f) {
+          set_flag(a.flags, FLAG_OVERFLOW);
+          ok = false;
+        }
+        int q = (int)floorf(lw * (float)(1 << (SH - 1)));
+        q = q < 0 ? 0 : (q > (1 << (SH + 1)) - 1 ? (1 << (SH + 1)) - 1 : q);
+        k[d] = kk;
+        cq[d] = q;
+      }
+      if (!ok) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = 0.0f;
+      }
+      const int dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1);
+      if constexpr (!SCATTER) {
+        long long q[4] = {0, 0, 0, 0};
+        if (active) {
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const double vd = (double)v[d];
+            q[d] = __double2ll_rn(vd * 4294967296.0);
+            q[3] += __double2ll_rn(vd * vd * 16777216.0);
+          }
+        }
+        const bool stay = active && dcode == 13;
+        const unsigned long long smask = __ballot(stay);
+        unsigned long long tot[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) tot[d] = wave_sum_u64(stay ? (unsigned long long)q[d] : 0ull);
+        if (lane == 0 && smask) {
+          atomicAdd(&grp[s * 27 + 13], (uint32_t)__popcll(smask));
+#pragma unroll
+          for (int d = 0; d < 4; ++d) atomicAdd(&mom[r_stay * 4 + d], tot[d]);
+        }
+        if (active && !stay) {
+          const int r = r_stay + k[0] + RG * (k[1] + RG * k[2]);
+          atomicAdd(&grp[s * 27 + dcode], 1u);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) atomicAdd(&mom[r * 4 + d], (unsigned long long)q[d]);
+        }
+      } else {
+        unsigned long long peers = __ballot(active);
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+          const bool bit = (dcode >> b) & 1;
+          const unsigned long long bb = __ballot(active && bit);
+          peers &= bit ? bb : ~bb;
+        }
+        const int rin = __popcll(peers & lt);
+        const int leader = active ? __ffsll((long long)peers) - 1 : lane;
+        uint32_t gbase = 0;
+        if (active && rin == 0) {
+          gbase = grp[s * 27 + dcode];
+          grp[s * 27 + dcode] = gbase + (uint32_t)__popcll(peers);
+        }
+        gbase = (uint32_t)__shfl((int)gbase, leader, 64);
+        if (active) {
+          const int nx = wrapi(g.cx0 + o0 + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
+          const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
+          const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
+          const uint64_t dst = a.off_n[cn] + a.slot[(int64_t)(26 - dcode) * a.nc3 + cn] + gbase + (uint32_t)rin;
+          if (dst < (uint64_t)a.cap) {
+            const float inv = a.vinv[cn];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const float u = (v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
+              nu_n[d * a.cap + dst] = (NT)encode_nu(u, edges, bucket, a.nbucket, a.vhalf);
+              chi_n[d * a.cap + dst] = (CT)cq[d];
+            }
+          } else {
+            set_flag(a.flags, FLAG_COUNT);
+          }
+        }
+      }
+    }
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(&next_cell, 1u);
+    s = __builtin_amdgcn_readfirstlane((int)t);
+  }
+  if constexpr (!SCATTER) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < TC * 27; i += NTH) {
+      const int s = i / 27, d = i % 27;
+      const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
+      a.mig[d * a.nc3 + c] = grp[i];
+    }
+    for (int i = threadIdx.x; i < RC * 4; i += NTH) {
+      const unsigned long long v = mom[i];
+      if (v == 0ull) continue;
+      const int r = i / 4, q = i % 4;
+      const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
+      const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
+      const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[q * a.nc3 + c]), v);
     }
   }
 }
@@ -886,9 +1166,15 @@ void launch_deposit(Sim& s, hipStream_t st) {
   a.pitch_f = (int64_t)s.mesh_plan.row_floats();
   a.nm = s.nm;
   a.nc = s.nc;
-  a.nt = s.nc / T;
+  a.nt = s.nc / DTX > 0 ? s.nc / DTX : 1;
+  // z chunks: enough workgroups to fill the chip, each chunk at least 4 coarse layers thick
+  const int cols = a.nt * a.nt;
+  int nchunk = 16384 / cols;
+  nchunk = nchunk < 1 ? 1 : (nchunk > s.nc / 4 ? s.nc / 4 : nchunk);
+  a.zc = (s.nc + nchunk - 1) / nchunk;
+  nchunk = (s.nc + a.zc - 1) / a.zc;
   a.inv_mean = (double)s.nm * (double)s.nm * (double)s.nm / ((double)s.n * ldexp(1.0, 3 * (8 * s.nchi - 1)));
-  const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
+  const dim3 grid((unsigned)cols, (unsigned)nchunk);
   if (s.nchi == 1) k_deposit<1><<<grid, BLK, 0, st>>>(a);
   else k_deposit<2><<<grid, BLK, 0, st>>>(a);
   CUBE_HIP(hipGetLastError());
@@ -974,14 +1260,14 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   const bool pre = mode == 0 && 2 * s.n >= (int64_t)s.nm * s.nm * s.nm;
 #define CUBE_COUNT(X, V)                                                                        \
   do {                                                                                          \
-    if (mode == 0 && pre) k_move_count<X, V, 0, true, 1024><<<grid, 1024, 0, st>>>(a);           \
+    if (mode == 0 && pre) k_move_dense<X, V, false><<<grid, 1024, 0, st>>>(a);                   \
     else if (mode == 0) k_move_count<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);              \
     else if (mode == 1) k_move_count<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);              \
     else k_move_count<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                             \
   } while (0)
 #define CUBE_SCATTER(X, V)                                                                      \
   do {                                                                                          \
-    if (mode == 0 && pre) k_move_scatter<X, V, 0, true, 1024><<<grid, 1024, 0, st>>>(a);         \
+    if (mode == 0 && pre) k_move_dense<X, V, true><<<grid, 1024, 0, st>>>(a);                    \
     else if (mode == 0) k_move_scatter<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);            \
     else if (mode == 1) k_move_scatter<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);            \
     else k_move_scatter<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                           \
