@@ -49,6 +49,27 @@ def algorithmic_bytes(cfg: dict) -> dict:
     }
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary
+    (calibrated against a plain copy), or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record:"):
+                continue
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if rec.get("kernel") != kernel:
+                continue
+            src = os.path.join(ROOT, rec["source"])
+            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+                return None
+            kib = float(rec["fetch_kib"]) * float(rec["fetch_scale"]) + float(rec["write_kib"]) * float(rec["write_scale"])
+            return kib * 1024.0
+    return None
+
+
 def cpu_baseline(cfg: dict, sample_side: int, steps: int):
     """The oracle (plain FP64 numpy PM on uncompressed particles) on a sub-box with the workload's
     particle and mesh resolution; particle-steps per second of host time."""
@@ -81,15 +102,169 @@ def cpu_baseline(cfg: dict, sample_side: int, steps: int):
     }
 
 
+def bench_ensemble(args) -> dict:
+    """The 64-box ensemble (synth.ensemble): all boxes stepped together with cube_batch_step (one
+    graph launch per step, variants autotuned per box shape) against the same boxes stepped one
+    after another with cube_step. Both legs time the same steps; box 0's state after them is
+    compared bit for bit."""
+    import numpy as np
+    import torch
+    from paper_1712_06121_amd import Batch, Sim
+
+    cfgs = synth.ensemble(n_steps=50)
+    total = sum(c["np_side"] ** 3 for c in cfgs)
+    print(f"[bench] ensemble: {len(cfgs)} boxes, {total / 1e6:.1f} M particles", file=sys.stderr, flush=True)
+    b = Batch(cfgs)
+    b.init_ic()
+    b.autotune()
+    b.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ref0 = b.boxes[0].get_state()
+    variants = sorted({(c["np_side"], box.variant) for c, box in zip(cfgs, b.boxes)})
+    dev_bytes = sum(box.device_bytes for box in b.boxes)
+    b.close()
+    print(f"[bench] batch: {args.steps} steps in {t_batch:.3f} s, variants {variants}", file=sys.stderr, flush=True)
+    t_seq = 0.0
+    same0 = None
+    for i, c in enumerate(cfgs):
+        with Sim(**c) as s:
+            s.init_ic()
+            s.step(args.warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(args.steps)
+            torch.cuda.synchronize()
+            t_seq += time.perf_counter() - t0
+            if i == 0:
+                st = s.get_state()
+                same0 = all(np.array_equal(st[k], ref0[k]) for k in ("cnt", "chi", "nu", "vc", "vs"))
+    print(f"[bench] sequential: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    step_bytes = sum(sum(algorithmic_bytes(c).values()) for c in cfgs)
+    k_step = t_batch / args.steps
+    return {
+        "metric": "particle-steps/s",
+        "value": total * args.steps / t_batch,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": k_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c4_ensemble: {len(cfgs)} boxes of 64^3..256^3 particles (mesh 2x, coarse mesh/4), "
+                               f"x1v1, n_s~U[0.9,1], sigma8~U[0.7,0.9], 50-step schedule; batched graph vs "
+                               f"sequential cube_step", "boxes": len(cfgs), "particles": total,
+                   "device_bytes": dev_bytes},
+        "roofline": {"bound": "hbm", "kernel": "whole ensemble step (graph)",
+                     "achieved": step_bytes / k_step / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": step_bytes / k_step / 1e9 / HBM_PEAK_GBS, "traffic": None},
+        "sequential": {"value": total * args.steps / t_seq, "seconds": t_seq},
+        "speedup_vs_sequential": t_seq / t_batch,
+        "box0_bit_identical": same0,
+        "cpu_baseline": None,
+    }
+
+
+def bench_serving(args) -> dict:
+    """The serving stream (synth.serving_jobs): requests arrive in real time at their Poisson
+    arrival times and are submitted to a cube_server; the loop polls it and records each job's
+    completion. Latency = completion - arrival; throughput = all particle-steps / wall time from
+    the first arrival to the last completion."""
+    from paper_1712_06121_amd import Server
+
+    jobs = synth.serving_jobs(n=args.serve_jobs)
+    total_ps = sum(j["cfg"]["np_side"] ** 3 * j["cfg"]["n_steps"] for j in jobs)
+    srv = Server(args.serve_budget_gb << 30, max_active=args.serve_slots, slice_steps=args.serve_slice)
+    # warm-up: one job of each size (first launches load the kernels), untimed
+    for i, side in enumerate((64, 128, 256)):
+        cfg = dict(next(j["cfg"] for j in jobs if j["cfg"]["np_side"] == side), seed=1 + i)
+        srv.submit(cfg, -1 - i)
+    left = {-1, -2, -3}
+    while left:
+        for i in srv.poll():
+            srv.release(i)
+            left.discard(i)
+        time.sleep(0.0005)
+    print(f"[bench] serving {len(jobs)} jobs over {jobs[-1]['arrival']:.1f} s of arrivals", file=sys.stderr,
+          flush=True)
+    done = {}
+    nxt = 0
+    max_active = 0
+    t0 = time.perf_counter()
+    last_print = t0
+    while len(done) < len(jobs):
+        now = time.perf_counter() - t0
+        while nxt < len(jobs) and jobs[nxt]["arrival"] <= now:
+            srv.submit(jobs[nxt]["cfg"], nxt)
+            nxt += 1
+        fin = srv.poll()
+        now = time.perf_counter() - t0
+        for i in fin:
+            st, rc = srv.status(i)
+            if st != Server.FINISHED:
+                raise RuntimeError(f"job {i} failed: {srv.job_error(i)}")
+            done[i] = now
+            srv.release(i)
+        max_active = max(max_active, srv.stats()[1])
+        if time.perf_counter() - last_print > 10.0:
+            last_print = time.perf_counter()
+            print(f"[bench] t={now:.1f} s: {len(done)} done, {nxt - len(done)} in the server", file=sys.stderr,
+                  flush=True)
+        if not fin:
+            time.sleep(0.0002)
+    srv.close()
+    lat = sorted(done[i] - jobs[i]["arrival"] for i in range(len(jobs)))
+    wall = max(done.values()) - jobs[0]["arrival"]
+    p50, p99 = lat[len(lat) // 2], lat[min(len(lat) - 1, int(0.99 * len(lat)))]
+    return {
+        "metric": "particle-steps/s",
+        "value": total_ps / wall,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": None,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"c5_serving: {len(jobs)} Poisson arrivals at 20 jobs/s, 64^3/128^3/256^3 particles "
+                               f"(p 0.5/0.35/0.15), mesh 2x, x1v1, sigma8~U[0.7,0.9], 50 steps",
+                   "slots": args.serve_slots, "slice_steps": args.serve_slice,
+                   "budget_GiB": args.serve_budget_gb},
+        "latency_s": {"p50": p50, "p99": p99, "mean": sum(lat) / len(lat), "max": lat[-1]},
+        "max_active_jobs": max_active,
+        "offered_particle_steps_per_s": total_ps / jobs[-1]["arrival"],
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3_pm2048", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--workload", default="c3_pm2048",
+                    choices=sorted(synth.WORKLOADS) + ["c4_ensemble", "c5_serving"])
+    ap.add_argument("--serve-jobs", type=int, default=600, help="c5_serving: number of requests (2000 = 100 s)")
+    ap.add_argument("--serve-slots", type=int, default=24)
+    ap.add_argument("--serve-slice", type=int, default=5)
+    ap.add_argument("--serve-budget-gb", type=int, default=160)
     ap.add_argument("--cpu-sample-side", type=int, default=128)
     ap.add_argument("--cpu-sample-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy (torch.neg) over 1 GiB, the reference reading that "
+                         "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -101,6 +276,19 @@ def main() -> int:
     from paper_1712_06121_amd import SIGMA_PER_CELL, Sim
 
     torch.cuda.set_device(0)
+    if args.workload == "c4_ensemble":
+        print(json.dumps(bench_ensemble(args)))
+        return 0
+    if args.workload == "c5_serving":
+        print(json.dumps(bench_serving(args)))
+        return 0
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.neg(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: torch.neg over {src.numel() * 4} bytes read, {dst.numel() * 4} written",
+              file=sys.stderr, flush=True)
+        del src, dst
     cfg = dict(synth.WORKLOADS[args.workload])
     if args.warmup + args.steps > cfg["n_steps"]:
         print(f"warmup + steps must not exceed the schedule's {cfg['n_steps']} steps", file=sys.stderr)
@@ -173,7 +361,7 @@ def main() -> int:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom) if args.workload == "c3_pm2048" else None,
             "algorithmic_bytes_per_launch": ab[dom],
             "avg_launch_ms": ms[dom],
         },

@@ -56,9 +56,11 @@ typedef struct cube_sim cube_sim;
  * a_init and a_final, uniform in ln a (spacing 0) or in a (spacing 1), integrated as DKD
  * leapfrog with merged drifts -- the paper's (DKKD)^n with the last half drift at the end. */
 typedef struct {
-  int32_t np_side;      /* particles per side of the initial lattice (N_p = np_side^3)          */
-  int32_t nm_side;      /* fine mesh cells per side; a power of two, 32 .. 2048                 */
-  int32_t nc_side;      /* coarse cells per side; nm_side / 4                                   */
+  int32_t np_side;      /* particles per side of the initial lattice (N_p = np_side^3); an FFT
+                           size (below) and a multiple of nc_side                                */
+  int32_t nm_side;      /* fine mesh cells per side, an FFT size: 2^k or 3*2^k in 32 .. 2048
+                           (32, 48, 64, 96, 128, 192, 256, 384, 512, 1024, 2048)                 */
+  int32_t nc_side;      /* coarse cells per side; nm_side / 4, a multiple of 8                  */
   int32_t x_bytes;      /* n_chi in {1, 2}: bytes per position code and dimension, Eq. (chi)    */
   int32_t v_bytes;      /* n_nu in {1, 2}: bytes per velocity code and dimension, Eq. (nu)      */
   int32_t sigma_mode;   /* CUBE_SIGMA_GLOBAL or CUBE_SIGMA_PER_CELL                             */
@@ -177,6 +179,93 @@ int64_t cube_device_bytes(const cube_sim* sim);
  * cube_set_profiling(sim, 1); it adds one host synchronisation per step. */
 int cube_set_profiling(cube_sim* sim, int enable);
 int cube_get_timings(const cube_sim* sim, double* ms9);
+
+/* ---- kernel variants and the autotuner ------------------------------------------------------
+ * Some stages have equivalent kernel variants that give bit-identical results: the move passes
+ * (move_variant 0: the 4-point gradient evaluated per CIC corner, 512-thread workgroups; 1: the
+ * gradient of the whole tile precomputed in LDS, one coarse cell per wavefront, 1024-thread
+ * workgroups; -1: chosen by particle density, the default) and the column width of the FFT's
+ * y/z passes (fft_col_width 8 or 16 complex values; 16 only for nm_side <= 512). */
+/* Time the variants on the current state (one deposit + solve, then moves whose result is
+ * discarded) and keep the fastest. The particle state is unchanged; the mesh afterwards holds the
+ * potential of the current state. Errors: CUBE_E_STATE (no particles). */
+int cube_autotune(cube_sim* sim);
+int cube_get_variant(const cube_sim* sim, int32_t* move_variant, int32_t* fft_col_width);
+/* Set the variants by hand (fft_col_width 0 keeps the current width). Errors: CUBE_E_INVALID. */
+int cube_set_variant(cube_sim* sim, int32_t move_variant, int32_t fft_col_width);
+
+/* ---- ensembles of independent boxes ----------------------------------------------------------
+ * A batch holds nbox simulations (box i created from params[i]; sizes, codecs and cosmologies may
+ * differ, n_steps must be equal), each on its own HIP stream created by the batch. One step of the
+ * whole ensemble is captured once into a HIP graph with one independent branch per box and
+ * replayed for every step (the kick and drift factors are read on the device from each box's
+ * schedule), so the boxes' kernels overlap on the GPU and the host makes one launch per step.
+ * Every box evolves exactly as it would alone: the results are bit-identical to stepping it by
+ * itself with cube_step. */
+typedef struct cube_batch cube_batch;
+
+/* `stream`: hipStream_t on which the step graphs are launched (NULL: a stream the batch creates,
+ * since a graph cannot be captured on the null stream); alloc as in
+ * cube_create. Errors: CUBE_E_INVALID (a box's parameters, unequal n_steps), CUBE_E_NOMEM,
+ * CUBE_E_DEVICE. The text of a failed create is cube_batch_last_error(NULL) on that thread. */
+int cube_batch_create(const cube_params* params, int32_t nbox, void* stream, const cube_allocator* alloc,
+                      cube_batch** out);
+void cube_batch_destroy(cube_batch* b);
+const char* cube_batch_last_error(const cube_batch* b);
+int32_t cube_batch_size(const cube_batch* b);
+/* Box i as a simulation handle owned by the batch (NULL if out of range). Single-box calls
+ * (state, density, power, ...) apply to it; stepping a box alone makes the batch refuse to step
+ * until the boxes are at the same step again (CUBE_E_STATE). */
+cube_sim* cube_batch_box(cube_batch* b, int32_t i);
+/* Initial conditions of every box (cube_init_ic on each). */
+int cube_batch_init_ic(cube_batch* b);
+/* cube_autotune on the first box of each distinct shape (mesh, lattice, codec); the choice is
+ * applied to every box of that shape. */
+int cube_batch_autotune(cube_batch* b);
+/* Advance every box k steps (one graph launch per step); the error flags of every box are
+ * checked once at the end. Returns CUBE_DONE when the boxes have reached a_final. */
+int cube_batch_step(cube_batch* b, int32_t k);
+
+/* ---- serving: continuous batching of simulation jobs -----------------------------------------
+ * A server runs independent jobs (one cube_params each) on one GPU. Jobs are queued in submission
+ * order; each scheduling round (cube_server_poll) checks the active jobs without waiting, enqueues
+ * the next slice of steps of those whose previous slice has finished, and admits queued jobs
+ * (oldest first) while their footprint fits the memory budget and an execution slot is free.
+ * Every active job has its own stream, so jobs that arrive while others run overlap with them on
+ * the device. Each job evolves exactly as it would alone: its state and P(k) are bit-identical to
+ * a cube_create / cube_init_ic / cube_step run of the same parameters. */
+typedef struct cube_server cube_server;
+
+/* Device bytes that cube_create followed by cube_init_ic allocates for these parameters at most
+ * (allocator rounding not included); negative (CUBE_E_INVALID) for malformed parameters. */
+int64_t cube_footprint(const cube_params* params);
+
+/* mem_budget_bytes: admission limit on the sum of the footprints of admitted, not yet released
+ * jobs; max_active: execution slots (jobs stepped concurrently); slice_steps: steps enqueued per
+ * job per round. alloc as in cube_create (used for every job's memory). */
+int cube_server_create(int64_t mem_budget_bytes, int32_t max_active, int32_t slice_steps,
+                       const cube_allocator* alloc, cube_server** out);
+/* Waits for every job's stream and frees everything. */
+void cube_server_destroy(cube_server* srv);
+const char* cube_server_last_error(const cube_server* srv);
+/* Queue a job under a caller-chosen id (unique among unreleased jobs). Errors: CUBE_E_INVALID,
+ * CUBE_E_CAPACITY (the footprint alone exceeds the budget). */
+int cube_server_submit(cube_server* srv, const cube_params* params, int64_t job_id);
+/* One scheduling round (never waits for the GPU). Writes up to max_finished ids of jobs that have
+ * finished or failed since the last poll into `finished` and their number into *n_finished;
+ * ids that do not fit are returned by later polls. */
+int cube_server_poll(cube_server* srv, int64_t* finished, int32_t max_finished, int32_t* n_finished);
+/* State of a job: 0 queued, 1 active, 2 finished, 3 failed (*rc = its error code; the text is
+ * cube_server_job_error). */
+int cube_server_status(const cube_server* srv, int64_t job_id, int32_t* state, int32_t* rc);
+const char* cube_server_job_error(const cube_server* srv, int64_t job_id);
+/* The simulation of a finished job (owned by the server, valid until released): read its state,
+ * density or P(k) with the single-box calls. NULL unless the job is finished. */
+cube_sim* cube_server_job(cube_server* srv, int64_t job_id);
+/* Free a finished or failed job's memory and forget its id. Errors: CUBE_E_STATE if it is still
+ * queued or active. */
+int cube_server_release(cube_server* srv, int64_t job_id);
+int cube_server_stats(const cube_server* srv, int32_t* queued, int32_t* active, int64_t* bytes_in_use);
 
 #ifdef __cplusplus
 }

@@ -5,8 +5,8 @@ package holds its sources (csrc/), the in-tree build (build.py) and the ctypes b
 (binding.py). Importing the package does not load the library; ``Sim`` does, and fails loudly
 when the library has not been built.
 """
-from .binding import (CUBE_DONE, CUBE_OK, EXPORTED, LIB_PATH, SIGMA_GLOBAL, SIGMA_PER_CELL, CubeError, Sim,
-                      load_library)
+from .binding import (CUBE_DONE, CUBE_OK, EXPORTED, LIB_PATH, SIGMA_GLOBAL, SIGMA_PER_CELL, Batch, CubeError, Server,
+                      Sim, footprint, load_library, make_params)
 
-__all__ = ["Sim", "CubeError", "load_library", "LIB_PATH", "EXPORTED", "SIGMA_GLOBAL", "SIGMA_PER_CELL", "CUBE_OK",
-           "CUBE_DONE"]
+__all__ = ["Sim", "Batch", "Server", "CubeError", "footprint", "load_library", "make_params", "LIB_PATH", "EXPORTED",
+           "SIGMA_GLOBAL", "SIGMA_PER_CELL", "CUBE_OK", "CUBE_DONE"]

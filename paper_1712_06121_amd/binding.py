@@ -27,7 +27,11 @@ EXPORTED = [
     "cube_scale_factor", "cube_steps_done", "cube_num_particles", "cube_get_density", "cube_get_power",
     "cube_get_state", "cube_set_state", "cube_stage_deposit", "cube_stage_solve", "cube_stage_move",
     "cube_get_mesh", "cube_set_mesh", "cube_get_ic_displacement", "cube_get_tables", "cube_get_schedule",
-    "cube_device_bytes", "cube_set_profiling", "cube_get_timings",
+    "cube_device_bytes", "cube_set_profiling", "cube_get_timings", "cube_autotune", "cube_get_variant",
+    "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
+    "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_footprint",
+    "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
+    "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
 
 
@@ -106,12 +110,84 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_device_bytes.restype = c_int64
     lib.cube_set_profiling.argtypes = [sim_p, c_int]
     lib.cube_get_timings.argtypes = [sim_p, c_void_p]
+    lib.cube_autotune.argtypes = [sim_p]
+    lib.cube_get_variant.argtypes = [sim_p, POINTER(c_int32), POINTER(c_int32)]
+    lib.cube_set_variant.argtypes = [sim_p, c_int32, c_int32]
+    batch_p = c_void_p
+    lib.cube_batch_create.argtypes = [POINTER(CubeParams), c_int32, c_void_p, POINTER(CubeAllocator), POINTER(c_void_p)]
+    lib.cube_batch_destroy.argtypes = [batch_p]
+    lib.cube_batch_destroy.restype = None
+    lib.cube_batch_last_error.argtypes = [batch_p]
+    lib.cube_batch_last_error.restype = c_char_p
+    lib.cube_batch_size.argtypes = [batch_p]
+    lib.cube_batch_size.restype = c_int32
+    lib.cube_batch_box.argtypes = [batch_p, c_int32]
+    lib.cube_batch_box.restype = c_void_p
+    for name in ("cube_batch_init_ic", "cube_batch_autotune"):
+        getattr(lib, name).argtypes = [batch_p]
+    lib.cube_batch_step.argtypes = [batch_p, c_int32]
+    lib.cube_footprint.argtypes = [POINTER(CubeParams)]
+    lib.cube_footprint.restype = c_int64
+    srv_p = c_void_p
+    lib.cube_server_create.argtypes = [c_int64, c_int32, c_int32, POINTER(CubeAllocator), POINTER(c_void_p)]
+    lib.cube_server_destroy.argtypes = [srv_p]
+    lib.cube_server_destroy.restype = None
+    lib.cube_server_last_error.argtypes = [srv_p]
+    lib.cube_server_last_error.restype = c_char_p
+    lib.cube_server_submit.argtypes = [srv_p, POINTER(CubeParams), c_int64]
+    lib.cube_server_poll.argtypes = [srv_p, c_void_p, c_int32, POINTER(c_int32)]
+    lib.cube_server_status.argtypes = [srv_p, c_int64, POINTER(c_int32), POINTER(c_int32)]
+    lib.cube_server_job_error.argtypes = [srv_p, c_int64]
+    lib.cube_server_job_error.restype = c_char_p
+    lib.cube_server_job.argtypes = [srv_p, c_int64]
+    lib.cube_server_job.restype = c_void_p
+    lib.cube_server_release.argtypes = [srv_p, c_int64]
+    lib.cube_server_stats.argtypes = [srv_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64)]
     _lib = lib
     return lib
 
 
 def _ptr(a: np.ndarray) -> c_void_p:
     return c_void_p(a.ctypes.data)
+
+
+def make_params(np_side: int, nm_side: int, box: float, nc_side: int | None = None, x_bytes: int = 1,
+                v_bytes: int = 1, sigma_mode: int = SIGMA_PER_CELL, omega_m: float = 0.3, omega_l: float | None = None,
+                h: float = 0.7, sigma8: float = 0.8, n_s: float = 1.0, a_init: float = 0.02, a_final: float = 1.0,
+                n_steps: int = 50, spacing: int = 0, seed: int = 1, capacity: int = 0, **_ignored) -> CubeParams:
+    """``cube_params`` from keyword arguments (omega_l defaults to a flat universe)."""
+    return CubeParams(np_side, nm_side, nc_side or nm_side // 4, x_bytes, v_bytes, sigma_mode, n_steps, spacing, box,
+                      omega_m, 1.0 - omega_m if omega_l is None else omega_l, h, sigma8, n_s, a_init, a_final, seed,
+                      capacity)
+
+
+def _torch_env(torch_memory: bool):
+    """PyTorch's current HIP stream and (optionally) its caching allocator as a cube_allocator.
+    Returns (stream, allocator pointer or None, objects to keep alive)."""
+    keep, stream, alloc_p = [], c_void_p(0), None
+    try:
+        import torch
+        if torch.cuda.is_available():
+            stream = c_void_p(torch.cuda.current_stream().cuda_stream)
+            if torch_memory:
+                dev = torch.cuda.current_device()
+                tstream = torch.cuda.current_stream()
+
+                def _alloc(nbytes, _user):
+                    try:
+                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, tstream)
+                    except Exception:  # out of memory: the library reports CUBE_E_NOMEM
+                        return None
+
+                def _free(ptr, _user):
+                    torch.cuda.caching_allocator_delete(ptr)
+
+                a = CubeAllocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+                keep.append(a)
+                alloc_p = byref(a)
+    except ImportError:
+        pass
+    return stream, alloc_p, keep
 
 
 class Sim:
@@ -121,44 +197,27 @@ class Sim:
                  v_bytes: int = 1, sigma_mode: int = SIGMA_PER_CELL, omega_m: float = 0.3, omega_l: float | None = None,
                  h: float = 0.7, sigma8: float = 0.8, n_s: float = 1.0, a_init: float = 0.02, a_final: float = 1.0,
                  n_steps: int = 50, spacing: int = 0, seed: int = 1, capacity: int = 0, torch_memory: bool = True,
-                 **_ignored):
+                 _handle: c_void_p | None = None, **_ignored):
         self._lib = load_library()
-        self.np_side, self.nm, self.nc = np_side, nm_side, nc_side or nm_side // 4
-        self.x_bytes, self.v_bytes, self.n_steps = x_bytes, v_bytes, n_steps
-        self.box = box
-        self.params = CubeParams(np_side, nm_side, self.nc, x_bytes, v_bytes, sigma_mode, n_steps, spacing, box,
-                                 omega_m, 1.0 - omega_m if omega_l is None else omega_l, h, sigma8, n_s, a_init,
-                                 a_final, seed, capacity)
-        self._keep = []
-        stream = c_void_p(0)
-        alloc_p = None
-        try:
-            import torch
-            if torch.cuda.is_available():
-                stream = c_void_p(torch.cuda.current_stream().cuda_stream)
-                if torch_memory:
-                    dev = torch.cuda.current_device()
-                    tstream = torch.cuda.current_stream()
-
-                    def _alloc(nbytes, _user):
-                        try:
-                            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, tstream)
-                        except Exception:  # out of memory: the library reports CUBE_E_NOMEM
-                            return None
-
-                    def _free(ptr, _user):
-                        torch.cuda.caching_allocator_delete(ptr)
-
-                    a = CubeAllocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
-                    self._keep.append(a)
-                    alloc_p = byref(a)
-        except ImportError:
-            pass
+        self.params = make_params(np_side, nm_side, box, nc_side, x_bytes, v_bytes, sigma_mode, omega_m, omega_l, h,
+                                  sigma8, n_s, a_init, a_final, n_steps, spacing, seed, capacity)
+        self._set_shape(self.params)
+        self._owned = _handle is None
+        if _handle is not None:  # a box owned by a Batch
+            self._h = _handle
+            self._keep = []
+            return
+        stream, alloc_p, self._keep = _torch_env(torch_memory)
         self._stream = stream
         self._h = c_void_p()
         rc = self._lib.cube_create(byref(self.params), stream, alloc_p, byref(self._h))
         if rc != CUBE_OK:
             raise CubeError(rc, "cube_create: " + self._lib.cube_last_error(None).decode())
+
+    def _set_shape(self, p: CubeParams):
+        self.np_side, self.nm, self.nc = p.np_side, p.nm_side, p.nc_side
+        self.x_bytes, self.v_bytes, self.n_steps = p.x_bytes, p.v_bytes, p.n_steps
+        self.box = p.box
 
     # ---- helpers -----------------------------------------------------------------------------
     def _check(self, rc: int) -> int:
@@ -168,7 +227,8 @@ class Sim:
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            self._lib.cube_destroy(self._h)
+            if self._owned:
+                self._lib.cube_destroy(self._h)
             self._h = c_void_p()
 
     def __del__(self):
@@ -298,3 +358,152 @@ class Sim:
         out = np.empty(9)
         self._check(self._lib.cube_get_timings(self._h, _ptr(out)))
         return out
+
+    # ---- kernel variants ---------------------------------------------------------------------
+    def autotune(self):
+        """Time the equivalent kernel variants on the current state and keep the fastest."""
+        self._check(self._lib.cube_autotune(self._h))
+
+    @property
+    def variant(self) -> tuple[int, int]:
+        """(move_variant, fft_col_width): -1 = by density, 0 = per-corner gradient, 1 = gradient tile."""
+        mv, bx = c_int32(), c_int32()
+        self._check(self._lib.cube_get_variant(self._h, byref(mv), byref(bx)))
+        return mv.value, bx.value
+
+    def set_variant(self, move_variant: int, fft_col_width: int = 0):
+        self._check(self._lib.cube_set_variant(self._h, move_variant, fft_col_width))
+
+
+class Batch:
+    """An ensemble of independent boxes stepped together (``cube_batch_*``): one HIP graph launch
+    per step for all boxes, each box on its own stream. ``boxes[i]`` is a ``Sim`` view of box i
+    (owned by the batch) for every single-box call."""
+
+    def __init__(self, configs: list[dict], torch_memory: bool = True):
+        self._lib = load_library()
+        n = len(configs)
+        arr = (CubeParams * n)(*[make_params(**c) for c in configs])
+        stream, alloc_p, self._keep = _torch_env(torch_memory)
+        self._h = c_void_p()
+        rc = self._lib.cube_batch_create(arr, n, stream, alloc_p, byref(self._h))
+        if rc != CUBE_OK:
+            raise CubeError(rc, "cube_batch_create: " + self._lib.cube_batch_last_error(None).decode())
+        self.boxes = [Sim(**c, _handle=c_void_p(self._lib.cube_batch_box(self._h, i))) for i, c in enumerate(configs)]
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise CubeError(rc, self._lib.cube_batch_last_error(self._h).decode())
+        return rc
+
+    def __len__(self):
+        return len(self.boxes)
+
+    def init_ic(self):
+        self._check(self._lib.cube_batch_init_ic(self._h))
+
+    def autotune(self):
+        self._check(self._lib.cube_batch_autotune(self._h))
+
+    def step(self, k: int = 1) -> int:
+        return self._check(self._lib.cube_batch_step(self._h, k))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            for b in self.boxes:
+                b._h = c_void_p()
+            self._lib.cube_batch_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def footprint(**cfg) -> int:
+    """Device bytes a simulation of these parameters allocates at most (``cube_footprint``)."""
+    lib = load_library()
+    fp = lib.cube_footprint(byref(make_params(**cfg)))
+    if fp < 0:
+        raise CubeError(fp, "cube_footprint: invalid parameters")
+    return fp
+
+
+class Server:
+    """Continuous-batching simulation server (``cube_server_*``): submit jobs at any time, call
+    ``poll()`` repeatedly; it returns the ids of jobs that finished (or failed) since the last
+    poll. ``job(id)`` is a ``Sim`` view of a finished job until ``release(id)``."""
+
+    QUEUED, ACTIVE, FINISHED, FAILED = 0, 1, 2, 3
+
+    def __init__(self, mem_budget_bytes: int, max_active: int = 16, slice_steps: int = 1, torch_memory: bool = True):
+        self._lib = load_library()
+        _, alloc_p, self._keep = _torch_env(torch_memory)
+        self._h = c_void_p()
+        rc = self._lib.cube_server_create(int(mem_budget_bytes), max_active, slice_steps, alloc_p, byref(self._h))
+        if rc != CUBE_OK:
+            raise CubeError(rc, "cube_server_create")
+        self._cfg = {}
+        self._buf = np.empty(1024, np.int64)
+
+    def _check(self, rc: int) -> int:
+        if rc < 0:
+            raise CubeError(rc, self._lib.cube_server_last_error(self._h).decode())
+        return rc
+
+    def submit(self, cfg: dict, job_id: int):
+        self._check(self._lib.cube_server_submit(self._h, byref(make_params(**cfg)), job_id))
+        self._cfg[job_id] = cfg
+
+    def poll(self) -> list[int]:
+        n = c_int32()
+        self._check(self._lib.cube_server_poll(self._h, _ptr(self._buf), len(self._buf), byref(n)))
+        return [int(x) for x in self._buf[: n.value]]
+
+    def status(self, job_id: int) -> tuple[int, int]:
+        st, rc = c_int32(), c_int32()
+        self._check(self._lib.cube_server_status(self._h, job_id, byref(st), byref(rc)))
+        return st.value, rc.value
+
+    def job_error(self, job_id: int) -> str:
+        return self._lib.cube_server_job_error(self._h, job_id).decode()
+
+    def job(self, job_id: int) -> Sim:
+        h = self._lib.cube_server_job(self._h, job_id)
+        if not h:
+            raise CubeError(-8, f"job {job_id} is not finished")
+        return Sim(**self._cfg[job_id], _handle=c_void_p(h))
+
+    def release(self, job_id: int):
+        self._check(self._lib.cube_server_release(self._h, job_id))
+        self._cfg.pop(job_id, None)
+
+    def stats(self) -> tuple[int, int, int]:
+        q, a, b = c_int32(), c_int32(), c_int64()
+        self._check(self._lib.cube_server_stats(self._h, byref(q), byref(a), byref(b)))
+        return q.value, a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.cube_server_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -24,6 +24,8 @@ PER_FILE = {
     "fft.hip": ["-ffp-contract=fast"],
     "api.cpp": ["-ffp-contract=off"],
     "cosmo.cpp": ["-ffp-contract=off"],
+    "batch.cpp": ["-ffp-contract=off"],
+    "serve.cpp": ["-ffp-contract=off"],
 }
 
 

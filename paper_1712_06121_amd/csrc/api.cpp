@@ -8,10 +8,6 @@
 
 #include "cube_internal.h"
 
-struct cube_sim {
-  cube::Sim s;
-};
-
 namespace {
 thread_local std::string g_create_error;  // text of the last failed cube_create on this thread
 }
@@ -51,9 +47,9 @@ void Sim::dfree(void* p) {
   else (void)hipFree(p);
 }
 
-namespace {
+// helpers shared with batch.cpp (declared in cube_internal.h)
 
-bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
 
 void build_tables(Sim& s) {
   const int m = (1 << (8 * s.nnu)) - 1;
@@ -180,6 +176,70 @@ void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps, b
   *wk_out = wk;
 }
 
+// Enqueue k steps on the simulation's stream (the initial half drift first if it is due) without
+// waiting for them; the device error flags are left for the caller to check. Returns CUBE_DONE
+// when a_final is reached before k steps.
+int enqueue_steps(Sim& s, int k) {
+  require_particles(s);
+  int rc = CUBE_OK;
+  if (s.profiling) {
+    for (double& t : s.timings) t = 0.0;
+    s.timing_calls = 0;
+  }
+  for (int i = 0; i < k; ++i) {
+    if (s.steps_done >= s.p.n_steps) {
+      rc = CUBE_DONE;
+      break;
+    }
+    if (!s.half_drift_done) {
+      launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+      s.half_drift_done = true;
+    }
+    const int j = s.steps_done;
+    // profiling events: [0,1] deposit, [2..7] five FFT passes, [8..11] count, link, scatter
+    hipEvent_t* ev = s.profiling ? s.ev : nullptr;
+    if (ev) CUBE_HIP(hipEventRecord(ev[0], s.stream));
+    launch_deposit(s, s.stream);
+    if (ev) CUBE_HIP(hipEventRecord(ev[1], s.stream));
+    fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, ev ? ev + 2 : nullptr);
+    launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream,
+                ev ? ev + 8 : nullptr);
+    if (ev) {
+      CUBE_HIP(hipEventSynchronize(ev[11]));
+      const int pairs[9][2] = {{0, 1}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {8, 9}, {9, 10}, {10, 11}};
+      for (int q = 0; q < 9; ++q) {
+        float ms = 0.f;
+        CUBE_HIP(hipEventElapsedTime(&ms, ev[pairs[q][0]], ev[pairs[q][1]]));
+        s.timings[q] += ms;
+      }
+      s.timing_calls++;
+    }
+    s.steps_done++;
+  }
+  return rc;
+}
+
+// Device bytes cube_create allocates for these parameters, plus the temporaries of
+// cube_init_ic (the transformed noise when the lattice and mesh sizes differ, the displacement
+// fields that do not fit in a particle buffer, the amplitude table). Mirrors the allocations of
+// cube_create, ic_fields and fft_plan_create.
+int64_t footprint_bytes(const cube_params& p) {
+  const int64_t nm = p.nm_side, nc = p.nc_side, np = p.np_side, nc3 = nc * nc * nc;
+  const int64_t cap = p.capacity > 0 ? p.capacity : np * np * np;
+  const int64_t pb = 3 * cap * (p.x_bytes + p.v_bytes);
+  auto field = [](int64_t n) { return n * n * (n / 2 + (n >= 1024 ? 8 : 16)) * 2 * (int64_t)sizeof(float); };
+  int64_t b = 2 * (pb + 4 * nc3 + 8 * (nc3 + 1) + 12 * nc3 + 4 * nc3);  // state, double buffered
+  b += 4 * nc3 + 2 * 108 * nc3 + 32 * nc3 + 8 * nc3;                  // vinv, mig, slot, mom, dev
+  b += 24 * ((nc3 + 255) / 256) + 64 + 16 + 24 * (nm / 2 + 1);       // link blocks, scalars, flags, P(k)
+  b += 12 * nm + (np != nm ? 12 * np : 0) + field(nm);               // FFT plans and the mesh
+  const int64_t m = ((int64_t)1 << (8 * p.v_bytes)) - 1;
+  b += 4 * m + 4 * (m - 1) + 2 * 4 * (m + 1);                         // codec tables
+  b += 8 * (int64_t)p.n_steps + 16;                                   // device schedule
+  const int64_t fl = field(np);
+  b += ((np != nm ? 1 : 0) + (pb >= fl ? 2 : 3)) * fl + 4 * (3 * (np / 2) * (np / 2) + 1);
+  return b;
+}
+
 int fail(cube_sim* sim, const Error& e) {
   if (sim) sim->s.last_error = e.msg;
   return e.code;
@@ -196,7 +256,6 @@ int fail(cube_sim* sim, const Error& e) {
     return ::cube::fail(sim, ::cube::Error{CUBE_E_INVALID, e.what()});                \
   }
 
-}  // namespace
 }  // namespace cube
 
 using cube::Error;
@@ -221,12 +280,12 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
       s.has_alloc = true;
     }
     const cube_params& p = s.p;
-    if (!cube::pow2(p.nm_side) || p.nm_side < 32 || p.nm_side > 2048)
-      throw Error{CUBE_E_INVALID, "nm_side must be a power of two in [32, 2048]"};
+    if (!cube::fft_size_supported(p.nm_side))
+      throw Error{CUBE_E_INVALID, "nm_side must be 2^k or 3*2^k in [32, 2048] (32, 48, 64, 96, ..., 1024, 2048)"};
     if (p.nc_side * 4 != p.nm_side) throw Error{CUBE_E_INVALID, "nc_side must be nm_side / 4"};
     if (p.nc_side % 8 != 0) throw Error{CUBE_E_INVALID, "nc_side must be a multiple of 8"};
-    if (!cube::pow2(p.np_side) || p.np_side < 32 || p.np_side > 2048 || p.np_side % p.nc_side != 0)
-      throw Error{CUBE_E_INVALID, "np_side must be a power of two in [32, 2048] and a multiple of nc_side"};
+    if (!cube::fft_size_supported(p.np_side) || p.np_side % p.nc_side != 0)
+      throw Error{CUBE_E_INVALID, "np_side must be 2^k or 3*2^k in [32, 2048] and a multiple of nc_side"};
     if (p.x_bytes < 1 || p.x_bytes > 2 || p.v_bytes < 1 || p.v_bytes > 2)
       throw Error{CUBE_E_INVALID, "x_bytes and v_bytes must be 1 or 2"};
     if (p.sigma_mode != CUBE_SIGMA_GLOBAL && p.sigma_mode != CUBE_SIGMA_PER_CELL)
@@ -277,6 +336,19 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
     else cube::fft_plan_create(s, s.lat_plan, s.np);
     s.mesh = static_cast<float*>(s.dmalloc(s.mesh_plan.field_floats() * sizeof(float)));
     cube::build_tables(s);
+    {
+      // the schedule's FP32 factors on the device, for replayed step graphs (same rounding as the
+      // immediate factors cube_step passes)
+      std::vector<float> kd(2 * (size_t)p.n_steps);
+      for (int j = 0; j < p.n_steps; ++j) {
+        kd[2 * j] = (float)(-s.kicks[j] / 12.0);
+        kd[2 * j + 1] = (float)s.drifts[j];
+      }
+      s.sched_dev = static_cast<float*>(s.dmalloc(sizeof(float) * kd.size()));
+      s.step_dev = static_cast<int*>(s.dmalloc(sizeof(int) * 4));
+      CUBE_HIP(hipMemcpy(s.sched_dev, kd.data(), sizeof(float) * kd.size(), hipMemcpyHostToDevice));
+      CUBE_HIP(hipMemsetAsync(s.step_dev, 0, sizeof(int) * 4, s.stream));
+    }
     CUBE_HIP(hipMemsetAsync(s.mom, 0, sizeof(int64_t) * 4 * s.nc3, s.stream));
     CUBE_HIP(hipMemsetAsync(s.flags, 0, sizeof(uint32_t) * 4, s.stream));
     CUBE_HIP(hipMemsetAsync(s.mesh, 0, s.mesh_plan.field_floats() * sizeof(float), s.stream));
@@ -372,51 +444,24 @@ int cube_load_particles(cube_sim* sim, const double* x, const double* v, int64_t
   return CUBE_OK;
 }
 
+int64_t cube_footprint(const cube_params* params) {
+  if (!params || params->np_side < 1 || params->nm_side < 1 || params->nc_side < 1 || params->x_bytes < 1 ||
+      params->x_bytes > 2 || params->v_bytes < 1 || params->v_bytes > 2 || params->n_steps < 1)
+    return CUBE_E_INVALID;
+  return cube::footprint_bytes(*params);
+}
+
 int cube_step(cube_sim* sim, int32_t k) {
   if (!sim || k < 0) return CUBE_E_INVALID;
   cube::Sim& s = sim->s;
   int rc = CUBE_OK;
   CUBE_GUARD(sim, {
-    cube::require_particles(s);
-    if (s.profiling) {
-      for (double& t : s.timings) t = 0.0;
-      s.timing_calls = 0;
-    }
-    for (int i = 0; i < k; ++i) {
-      if (s.steps_done >= s.p.n_steps) {
-        rc = CUBE_DONE;
-        break;
-      }
-      if (!s.half_drift_done) {
-        cube::launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
-        s.half_drift_done = true;
-      }
-      const int j = s.steps_done;
-      // profiling events: [0,1] deposit, [2..7] five FFT passes, [8..11] count, link, scatter
-      hipEvent_t* ev = s.profiling ? s.ev : nullptr;
-      if (ev) CUBE_HIP(hipEventRecord(ev[0], s.stream));
-      cube::launch_deposit(s, s.stream);
-      if (ev) CUBE_HIP(hipEventRecord(ev[1], s.stream));
-      cube::fft_solve_poisson(s.mesh_plan, s.mesh, cube::gconst(s), s.stream, ev ? ev + 2 : nullptr);
-      cube::launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream,
-                        ev ? ev + 8 : nullptr);
-      if (ev) {
-        CUBE_HIP(hipEventSynchronize(ev[11]));
-        const int pairs[9][2] = {{0, 1}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {8, 9}, {9, 10}, {10, 11}};
-        for (int q = 0; q < 9; ++q) {
-          float ms = 0.f;
-          CUBE_HIP(hipEventElapsedTime(&ms, ev[pairs[q][0]], ev[pairs[q][1]]));
-          s.timings[q] += ms;
-        }
-        s.timing_calls++;
-      }
-      s.steps_done++;
-    }
+    rc = cube::enqueue_steps(s, k);
     cube::check_flags(s);
-    if (s.steps_done >= s.p.n_steps && rc == CUBE_OK && k > 0) rc = CUBE_OK;
   });
   return rc;
 }
+
 
 double cube_scale_factor(const cube_sim* sim) {
   if (!sim) return 0.0;

@@ -1,0 +1,357 @@
+// Ensembles of independent boxes stepped together, and the variant autotuner.
+//
+// A batch owns one simulation per box, each on its own HIP stream. One step of the whole ensemble
+// (deposit, five-pass Poisson solve, count / link / scatter move passes and a step-counter bump
+// per box) is captured once into a HIP graph in which every box is an independent branch, so the
+// boxes' kernels overlap on the device and the host launches one graph per step. The kick and drift
+// factors of each step are read on the device from the box's schedule table, so the same graph
+// is replayed for every step; two graphs are kept, one per parity of the double-buffered state.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "cube_internal.h"
+
+struct cube_batch {
+  std::vector<cube_sim*> boxes;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
+  hipStream_t main = nullptr;
+  bool own_main = false;  // graphs cannot be captured on the null stream: the batch then makes its own
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::string last_error;
+};
+
+namespace cube {
+namespace {
+
+thread_local std::string g_batch_create_error;
+
+int batch_fail(cube_batch* b, const Error& e) {
+  if (b) b->last_error = e.msg;
+  return e.code;
+}
+
+#define CUBE_BATCH_GUARD(b, ...)                                                      \
+  try {                                                                               \
+    __VA_ARGS__;                                                                      \
+  } catch (const ::cube::Error& e) {                                                  \
+    return ::cube::batch_fail(b, e);                                                  \
+  } catch (const std::bad_alloc&) {                                                   \
+    return ::cube::batch_fail(b, ::cube::Error{CUBE_E_NOMEM, "host allocation failed"}); \
+  } catch (const std::exception& e) {                                                 \
+    return ::cube::batch_fail(b, ::cube::Error{CUBE_E_INVALID, e.what()});            \
+  }
+
+// one step of a box on stream st with the factors taken from the device schedule
+void enqueue_graph_step(Sim& s, hipStream_t st) {
+  launch_deposit(s, st);
+  fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), st, nullptr);
+  launch_move(s, 0, 0.0f, 0.0f, nullptr, 0.0f, st, nullptr, true);
+  launch_advance_step(s, st);
+}
+
+void destroy_graphs(cube_batch& b) {
+  for (int p = 0; p < 2; ++p) {
+    if (b.exec[p]) (void)hipGraphExecDestroy(b.exec[p]);
+    if (b.graph[p]) (void)hipGraphDestroy(b.graph[p]);
+    b.exec[p] = nullptr;
+    b.graph[p] = nullptr;
+  }
+}
+
+// capture one ensemble step starting from state parity `par` (every box has cur == par)
+void build_graph(cube_batch& b, int par) {
+  CUBE_HIP(hipStreamBeginCapture(b.main, hipStreamCaptureModeRelaxed));
+  try {
+    CUBE_HIP(hipEventRecord(b.fork, b.main));
+    for (size_t i = 0; i < b.boxes.size(); ++i) {
+      Sim& s = b.boxes[i]->s;
+      CUBE_HIP(hipStreamWaitEvent(b.streams[i], b.fork, 0));
+      enqueue_graph_step(s, b.streams[i]);
+      s.cur = par;  // the capture flipped the host-side parity; replays flip it instead
+      CUBE_HIP(hipEventRecord(b.joins[i], b.streams[i]));
+      CUBE_HIP(hipStreamWaitEvent(b.main, b.joins[i], 0));
+    }
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(b.main, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  CUBE_HIP(hipStreamEndCapture(b.main, &b.graph[par]));
+  CUBE_HIP(hipGraphInstantiate(&b.exec[par], b.graph[par], nullptr, nullptr, 0));
+}
+
+float elapsed_ms(hipEvent_t a, hipEvent_t z) {
+  CUBE_HIP(hipEventSynchronize(z));
+  float ms = 0.f;
+  CUBE_HIP(hipEventElapsedTime(&ms, a, z));
+  return ms;
+}
+
+// Time the equivalent variants of the FFT column passes and of the move passes on the current
+// state and keep the fastest. The particle state is left unchanged (timed moves write only the
+// next-state buffers and scratch, and the parity is restored); the mesh is left holding the
+// potential of the current state.
+void autotune_sim(Sim& s) {
+  require_particles(s);
+  hipEvent_t e0 = s.ev[14], e1 = s.ev[15];
+  constexpr int reps = 2;
+  // FFT column width
+  int best_bx = s.mesh_plan.colbx;
+  float best = 1e30f;
+  for (int bx : fft_col_widths(s.nm)) {
+    s.mesh_plan.colbx = bx;
+    float t = 0.f;
+    for (int r = 0; r <= reps; ++r) {
+      launch_deposit(s, s.stream);
+      CUBE_HIP(hipEventRecord(e0, s.stream));
+      fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+      CUBE_HIP(hipEventRecord(e1, s.stream));
+      const float ms = elapsed_ms(e0, e1);
+      if (r > 0) t += ms;  // the first run warms up
+    }
+    if (t < best) {
+      best = t;
+      best_bx = bx;
+    }
+  }
+  s.mesh_plan.colbx = best_bx;
+  launch_deposit(s, s.stream);
+  fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+  // move passes: per-corner gradient vs precomputed gradient tile, with this step's factors
+  const int j = std::min(s.steps_done, s.p.n_steps - 1);
+  const float kf = (float)(-s.kicks[j] / 12.0), df = (float)s.drifts[j];
+  int best_v = 0;
+  best = 1e30f;
+  for (int v = 0; v <= 1; ++v) {
+    s.move_variant = v;
+    float t = 0.f;
+    for (int r = 0; r <= reps; ++r) {
+      const int cur = s.cur;
+      CUBE_HIP(hipEventRecord(e0, s.stream));
+      launch_move(s, 0, kf, df, nullptr, 0.0f, s.stream, nullptr);
+      CUBE_HIP(hipEventRecord(e1, s.stream));
+      s.cur = cur;  // discard the result
+      const float ms = elapsed_ms(e0, e1);
+      if (r > 0) t += ms;
+    }
+    if (t < best) {
+      best = t;
+      best_v = v;
+    }
+  }
+  s.move_variant = best_v;
+  // a timed move may have raised a flag that the real step will raise again; clear it here
+  CUBE_HIP(hipMemsetAsync(s.flags, 0, sizeof(uint32_t), s.stream));
+  CUBE_HIP(hipStreamSynchronize(s.stream));
+}
+
+}  // namespace
+}  // namespace cube
+
+using cube::Error;
+
+extern "C" {
+
+int cube_autotune(cube_sim* sim) {
+  if (!sim) return CUBE_E_INVALID;
+  try {
+    cube::autotune_sim(sim->s);
+  } catch (const Error& e) {
+    sim->s.last_error = e.msg;
+    return e.code;
+  } catch (const std::exception& e) {
+    sim->s.last_error = e.what();
+    return CUBE_E_INVALID;
+  }
+  return CUBE_OK;
+}
+
+int cube_get_variant(const cube_sim* sim, int32_t* move_variant, int32_t* fft_col_width) {
+  if (!sim) return CUBE_E_INVALID;
+  if (move_variant) *move_variant = sim->s.move_variant;
+  if (fft_col_width) *fft_col_width = sim->s.mesh_plan.colbx;
+  return CUBE_OK;
+}
+
+int cube_set_variant(cube_sim* sim, int32_t move_variant, int32_t fft_col_width) {
+  if (!sim) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  if (move_variant < -1 || move_variant > 1) {
+    s.last_error = "move_variant must be -1, 0 or 1";
+    return CUBE_E_INVALID;
+  }
+  if (fft_col_width != 0) {
+    const std::vector<int> ok = cube::fft_col_widths(s.nm);
+    if (std::find(ok.begin(), ok.end(), fft_col_width) == ok.end()) {
+      s.last_error = "unsupported FFT column width for this mesh size";
+      return CUBE_E_INVALID;
+    }
+    s.mesh_plan.colbx = fft_col_width;
+  }
+  s.move_variant = move_variant;
+  return CUBE_OK;
+}
+
+int cube_batch_create(const cube_params* params, int32_t nbox, void* stream, const cube_allocator* alloc,
+                      cube_batch** out) {
+  if (!params || !out || nbox < 1) return CUBE_E_INVALID;
+  *out = nullptr;
+  cube_batch* b = nullptr;
+  try {
+    b = new cube_batch();
+  } catch (...) {
+    return CUBE_E_NOMEM;
+  }
+  try {
+    b->main = static_cast<hipStream_t>(stream);
+    if (!b->main) {
+      CUBE_HIP(hipStreamCreateWithFlags(&b->main, hipStreamNonBlocking));
+      b->own_main = true;
+    }
+    for (int i = 1; i < nbox; ++i)
+      if (params[i].n_steps != params[0].n_steps) throw Error{CUBE_E_INVALID, "every box must have the same n_steps"};
+    CUBE_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    for (int i = 0; i < nbox; ++i) {
+      hipStream_t st = nullptr;
+      CUBE_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      b->streams.push_back(st);
+      hipEvent_t ev = nullptr;
+      CUBE_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      b->joins.push_back(ev);
+      cube_sim* sim = nullptr;
+      const int rc = cube_create(&params[i], st, alloc, &sim);
+      if (rc != CUBE_OK) throw Error{rc, "box " + std::to_string(i) + ": " + cube_last_error(nullptr)};
+      b->boxes.push_back(sim);
+    }
+  } catch (const Error& e) {
+    cube::g_batch_create_error = e.msg;
+    cube_batch_destroy(b);
+    return e.code;
+  } catch (const std::exception& e) {
+    cube::g_batch_create_error = e.what();
+    cube_batch_destroy(b);
+    return CUBE_E_NOMEM;
+  }
+  *out = b;
+  return CUBE_OK;
+}
+
+void cube_batch_destroy(cube_batch* b) {
+  if (!b) return;
+  if (b->main) (void)hipStreamSynchronize(b->main);
+  cube::destroy_graphs(*b);
+  for (cube_sim* s : b->boxes) cube_destroy(s);
+  for (hipStream_t st : b->streams) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->joins) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->own_main) (void)hipStreamDestroy(b->main);
+  delete b;
+}
+
+const char* cube_batch_last_error(const cube_batch* b) {
+  return b ? b->last_error.c_str() : cube::g_batch_create_error.c_str();
+}
+
+int32_t cube_batch_size(const cube_batch* b) { return b ? (int32_t)b->boxes.size() : 0; }
+
+cube_sim* cube_batch_box(cube_batch* b, int32_t i) {
+  if (!b || i < 0 || i >= (int32_t)b->boxes.size()) return nullptr;
+  return b->boxes[i];
+}
+
+int cube_batch_init_ic(cube_batch* b) {
+  if (!b) return CUBE_E_INVALID;
+  for (size_t i = 0; i < b->boxes.size(); ++i) {
+    const int rc = cube_init_ic(b->boxes[i]);
+    if (rc != CUBE_OK) {
+      b->last_error = "box " + std::to_string(i) + ": " + cube_last_error(b->boxes[i]);
+      return rc;
+    }
+  }
+  cube::destroy_graphs(*b);
+  return CUBE_OK;
+}
+
+int cube_batch_autotune(cube_batch* b) {
+  if (!b) return CUBE_E_INVALID;
+  // one measurement per distinct box shape, applied to every box of that shape
+  std::map<std::tuple<int, int, int, int>, std::pair<int, int>> chosen;
+  for (size_t i = 0; i < b->boxes.size(); ++i) {
+    cube::Sim& s = b->boxes[i]->s;
+    const auto key = std::make_tuple(s.nm, s.np, s.nchi, s.nnu);
+    auto it = chosen.find(key);
+    if (it == chosen.end()) {
+      const int rc = cube_autotune(b->boxes[i]);
+      if (rc != CUBE_OK) {
+        b->last_error = "box " + std::to_string(i) + ": " + cube_last_error(b->boxes[i]);
+        return rc;
+      }
+      chosen[key] = {s.move_variant, s.mesh_plan.colbx};
+    } else {
+      s.move_variant = it->second.first;
+      s.mesh_plan.colbx = it->second.second;
+    }
+  }
+  cube::destroy_graphs(*b);  // the captured kernels depend on the variants
+  return CUBE_OK;
+}
+
+int cube_batch_step(cube_batch* b, int32_t k) {
+  if (!b || k < 0) return CUBE_E_INVALID;
+  int rc = CUBE_OK;
+  CUBE_BATCH_GUARD(b, {
+    std::vector<cube::Sim*> ss;
+    for (cube_sim* x : b->boxes) ss.push_back(&x->s);
+    for (cube::Sim* s : ss) cube::require_particles(*s);
+    const int done = ss[0]->steps_done;
+    for (cube::Sim* s : ss)
+      if (s->steps_done != done || s->cur != ss[0]->cur)
+        throw Error{CUBE_E_STATE, "boxes of a batch must be at the same step (step them with cube_batch_step only)"};
+    // the initial half drift (no force) of every box, each on its own stream
+    for (size_t i = 0; i < ss.size(); ++i) {
+      cube::Sim& s = *ss[i];
+      if (!s.half_drift_done) {
+        cube::launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+        s.half_drift_done = true;
+      }
+    }
+    for (size_t i = 0; i < ss.size(); ++i) {
+      cube::Sim& s = *ss[i];
+      CUBE_HIP(hipMemcpyAsync(s.step_dev, &s.steps_done, sizeof(int), hipMemcpyHostToDevice, s.stream));
+      CUBE_HIP(hipEventRecord(b->joins[i], s.stream));
+      CUBE_HIP(hipStreamWaitEvent(b->main, b->joins[i], 0));
+    }
+    // the upload above reads host memory asynchronously: keep it alive until it has landed
+    CUBE_HIP(hipStreamSynchronize(b->main));
+    for (int i = 0; i < k; ++i) {
+      if (ss[0]->steps_done >= ss[0]->p.n_steps) {
+        rc = CUBE_DONE;
+        break;
+      }
+      const int par = ss[0]->cur;
+      if (!b->exec[par]) cube::build_graph(*b, par);
+      CUBE_HIP(hipGraphLaunch(b->exec[par], b->main));
+      for (cube::Sim* s : ss) {
+        s->cur ^= 1;
+        s->steps_done++;
+      }
+    }
+    CUBE_HIP(hipStreamSynchronize(b->main));
+    for (size_t i = 0; i < ss.size(); ++i) {
+      try {
+        cube::check_flags(*ss[i]);
+      } catch (const Error& e) {
+        throw Error{e.code, "box " + std::to_string(i) + ": " + e.msg};
+      }
+    }
+  });
+  return rc;
+}
+
+}  // extern "C"

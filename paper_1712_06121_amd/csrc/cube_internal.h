@@ -39,7 +39,8 @@ enum : uint32_t {
 // columns beyond N/2 are padding processed as don't-care values.
 struct FFTPlan {
   int n = 0;
-  int bx = 0;        // column block width of the y/z passes (complex values)
+  int bx = 0;        // row padding (complex values): the widest column block of the y/z passes
+  int colbx = 0;     // column block width used by the y/z passes (8 or 16; tunable)
   int pitch_c = 0;   // complex values per row, = n/2 + bx
   float2* tw = nullptr;    // exp(-2 pi i t / n), t = 0..n-1 (device)
   float* k2 = nullptr;     // (2 pi f(t) / n)^2 with f the signed frequency of index t (device)
@@ -101,8 +102,11 @@ struct Sim {
   Cosmo cosmo{};
   std::vector<double> a_int, a_half, kicks, drifts;
   double drift0 = 0.0;
+  float* sched_dev = nullptr;  // FP32 (-kick_j / 12, drift_j) per step (device)
+  int* step_dev = nullptr;     // step index read by graph-replayed move kernels (device)
   int steps_done = 0;
   bool half_drift_done = false;
+  int move_variant = -1;  // move passes: -1 by particle density, 0 per-corner gradient, 1 gradient tile
   double a_now = 0.0;
   bool have_particles = false;
 
@@ -120,7 +124,16 @@ struct Sim {
   std::vector<size_t> sizes;
 };
 
+// ---- host helpers (api.cpp) ------------------------------------------------------------------
+void check_flags(Sim& s);         // reads and clears the device error flags; throws on a set flag
+float gconst(const Sim& s);       // Green's constant -3/2 Omega_m / N^3
+void require_particles(const Sim& s);
+int enqueue_steps(Sim& s, int k);  // k steps on s.stream, no wait, flags unchecked; CUBE_DONE at a_final
+int64_t footprint_bytes(const cube_params& p);
+
 // ---- launchers (implemented in the .hip files) ---------------------------------------------
+bool fft_size_supported(int n);
+std::vector<int> fft_col_widths(int n);  // column block widths the y/z passes support at size n
 void fft_plan_create(Sim& s, FFTPlan& pl, int n);
 void fft_plan_destroy(Sim& s, FFTPlan& pl);
 void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st);
@@ -134,9 +147,15 @@ void fft_ic_component(const FFTPlan& pl, const float* wk, float* out, const floa
 void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st);
 void launch_deposit(Sim& s, hipStream_t st);
 // move: mode 0 = step (force from mesh), 1 = drift only (no force), 2 = initial conditions
+// dev_sched: take the kick/drift factors of step *step_dev from sched_dev (for captured graphs)
 void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
-                 hipEvent_t* evs);
+                 hipEvent_t* evs, bool dev_sched = false);
+void launch_advance_step(Sim& s, hipStream_t st);
 void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream_t st);
 void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmodes);
 
 }  // namespace cube
+
+struct cube_sim {
+  cube::Sim s;
+};

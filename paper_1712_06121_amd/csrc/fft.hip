@@ -19,7 +19,11 @@ namespace cube {
 namespace {
 
 constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
-constexpr int first_radix(int l) { return (ilog2c(l) % 3 == 1) ? 2 : ((ilog2c(l) % 3 == 2) ? 4 : 8); }
+// radix of the next stage for a remaining length `rem` (3 * 2^m or 2^m): the factor 3 first, then
+// one radix-2 or radix-4 stage so that the rest is a power of 8
+constexpr int next_radix(int rem) {
+  return rem % 3 == 0 ? 3 : ((ilog2c(rem) % 3 == 1) ? 2 : ((ilog2c(rem) % 3 == 2) ? 4 : 8));
+}
 
 __device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
@@ -56,6 +60,23 @@ __device__ __forceinline__ void dft<2, 1>(float2* v) {
   v[0] = a + b;
   v[1] = a - b;
 }
+
+// length-3 DFT: y_k = sum_j v_j exp(DIR 2 pi i j k / 3)
+template <int DIR>
+__device__ __forceinline__ void dft3(float2* v) {
+  const float h = 0.86602540378443864676f * (float)DIR;  // DIR * sqrt(3) / 2
+  const float2 t1 = v[1] + v[2];
+  const float2 d = v[1] - v[2];
+  const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  const float2 iu = make_float2(-h * d.y, h * d.x);
+  v[0] = v[0] + t1;
+  v[1] = t2 + iu;
+  v[2] = t2 - iu;
+}
+template <>
+__device__ __forceinline__ void dft<3, -1>(float2* v) { dft3<-1>(v); }
+template <>
+__device__ __forceinline__ void dft<3, 1>(float2* v) { dft3<1>(v); }
 
 template <int DIR>
 __device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
@@ -140,17 +161,25 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* __rest
 template <int L, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw) {
   if constexpr (NS < L) {
-    constexpr int R = (NS == 1) ? first_radix(L) : 8;
+    constexpr int R = next_radix(L / NS);
     stockham_stage<L, R, NS, NL, LS, TS, BLOCK, DIR, TWS>(lds, tw);
     fft_lds<L, NS * R, NL, LS, TS, BLOCK, DIR, TWS>(lds, tw);
   }
 }
 
 // ---- x pass: real rows <-> half spectrum ---------------------------------------------------
+// rows per workgroup: the largest power of two with at most 2048 complex values in LDS that
+// divides the row count
+constexpr int rows_per_block(int n) {
+  int nl = 1;
+  while (2 * nl * (n / 2) <= 2048 && (n * n) % (2 * nl) == 0) nl *= 2;
+  return nl;
+}
+
 template <int N>
 struct RowCfg {
   static constexpr int H = N / 2;
-  static constexpr int NL = (2048 / H) < 1 ? 1 : 2048 / H;
+  static constexpr int NL = rows_per_block(N);
   static constexpr int BLOCK = 256;
 };
 
@@ -161,21 +190,23 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
   __shared__ float2 lds[NL * H];
   const int64_t row0 = (int64_t)blockIdx.x * NL;
   constexpr int F4 = N / 4;
-  constexpr int LPT = NL * F4 / BLOCK;
-  static_assert(NL * F4 % BLOCK == 0, "block must divide the rows");
+  constexpr int LPT = (NL * F4 + BLOCK - 1) / BLOCK;
   float4 stage[LPT];
 #pragma unroll
   for (int k = 0; k < LPT; ++k) {
     const int i = threadIdx.x + k * BLOCK;
     const int l = i / F4, c = i % F4;
-    stage[k] = *reinterpret_cast<const float4*>(data + (row0 + l) * pitch_f + 4 * c);
+    if ((NL * F4) % BLOCK == 0 || i < NL * F4)
+      stage[k] = *reinterpret_cast<const float4*>(data + (row0 + l) * pitch_f + 4 * c);
   }
 #pragma unroll
   for (int k = 0; k < LPT; ++k) {
     const int i = threadIdx.x + k * BLOCK;
     const int l = i / F4, c = i % F4;
-    lds[l * H + 2 * c] = make_float2(stage[k].x, stage[k].y);
-    lds[l * H + 2 * c + 1] = make_float2(stage[k].z, stage[k].w);
+    if ((NL * F4) % BLOCK == 0 || i < NL * F4) {
+      lds[l * H + 2 * c] = make_float2(stage[k].x, stage[k].y);
+      lds[l * H + 2 * c + 1] = make_float2(stage[k].z, stage[k].w);
+    }
   }
   __syncthreads();
   fft_lds<H, 1, NL, H, 1, BLOCK, -1, 2>(lds, tw);
@@ -183,7 +214,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
   for (int i = threadIdx.x; i < NL * NP; i += BLOCK) {
     const int l = i / NP, k = i % NP;
     const float2 zk = lds[l * H + k];
-    const float2 zm = conjf2(lds[l * H + ((H - k) & (H - 1))]);
+    const float2 zm = conjf2(lds[l * H + (k == 0 ? 0 : H - k)]);
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
     const float2 dd = zk - zm;
     const float2 o = make_float2(0.5f * dd.y, -0.5f * dd.x);
@@ -238,11 +269,15 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
 }
 
 // ---- y / z passes: blocks of BX columns ------------------------------------------------------
-template <int N>
+// BX: complex columns per workgroup (8 or 16; 16 needs N <= 512 to fit LDS). The pitch of the
+// padded rows always leaves room for 16.
+template <int N, int BX>
 struct ColCfg {
-  static constexpr int BX = (N >= 2048) ? 8 : ((N >= 1024) ? 8 : 16);
-  static constexpr int BLOCK = (N >= 2048) ? 512 : 256;
+  static constexpr int NQ = N * BX / 2;
+  static constexpr int BLOCK = (N >= 2048) ? 512 : (NQ % 256 == 0 ? 256 : (NQ % 128 == 0 ? 128 : 64));
 };
+constexpr int col_bx_default(int n) { return n >= 1024 ? 8 : 16; }
+constexpr int col_bx_pitch(int n) { return n >= 1024 ? 8 : 16; }
 
 enum ColMode { COL_FWD = 0, COL_INV = 1, COL_GREEN = 2, COL_POWER = 3, COL_PSI = 4 };
 
@@ -257,11 +292,11 @@ struct ColArgs {
 
 __device__ __forceinline__ int signed_freq(int t, int n) { return t <= n / 2 ? t : t - n; }
 
-template <int N, int MODE>
-__global__ __launch_bounds__(ColCfg<N>::BLOCK) void k_fft_col(const float2* __restrict__ src, float2* __restrict__ dst,
-                                                             int64_t tstride, int64_t ostride,
-                                                             const float2* __restrict__ tw, ColArgs a) {
-  constexpr int BX = ColCfg<N>::BX, BLOCK = ColCfg<N>::BLOCK;
+template <int N, int MODE, int BX>
+__global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                                 int64_t tstride, int64_t ostride,
+                                                                 const float2* __restrict__ tw, ColArgs a) {
+  constexpr int BLOCK = ColCfg<N, BX>::BLOCK;
   __shared__ float2 lds[N * BX];
   const int cb = blockIdx.x, o = blockIdx.y;
   const int64_t base = (int64_t)o * ostride + (int64_t)cb * BX;
@@ -367,16 +402,28 @@ void run_x(const FFTPlan& pl, float* data, bool forward, hipStream_t st) {
   CUBE_HIP(hipGetLastError());
 }
 
-template <int N, int MODE>
-void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
-  const int ncb = (N / 2) / ColCfg<N>::BX + 1;
+template <int N, int MODE, int BX>
+void run_col_bx(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
+  const int ncb = (N / 2) / BX + 1;  // the last block holds the Nyquist column and padding
   const int64_t pc = pl.pitch_c;
   const int64_t tstride = axis == 1 ? pc : (int64_t)N * pc;
   const int64_t ostride = axis == 1 ? (int64_t)N * pc : pc;
   const dim3 grid(ncb, N);
-  k_fft_col<N, MODE><<<grid, ColCfg<N>::BLOCK, 0, st>>>(reinterpret_cast<const float2*>(src),
-                                                        reinterpret_cast<float2*>(dst), tstride, ostride, pl.tw, a);
+  k_fft_col<N, MODE, BX><<<grid, ColCfg<N, BX>::BLOCK, 0, st>>>(reinterpret_cast<const float2*>(src),
+                                                                reinterpret_cast<float2*>(dst), tstride, ostride,
+                                                                pl.tw, a);
   CUBE_HIP(hipGetLastError());
+}
+
+template <int N, int MODE>
+void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
+  if constexpr (N < 1024) {
+    if (pl.colbx == 16) {
+      run_col_bx<N, MODE, 16>(pl, src, dst, axis, a, st);
+      return;
+    }
+  }
+  run_col_bx<N, MODE, 8>(pl, src, dst, axis, a, st);
 }
 
 template <int N>
@@ -422,25 +469,35 @@ void ic_n(const FFTPlan& pl, const float* wk, float* out, const float* tab, int 
 #define CUBE_FFT_DISPATCH(n, CALL)                        \
   switch (n) {                                            \
     case 32: CALL(32); break;                             \
+    case 48: CALL(48); break;                             \
     case 64: CALL(64); break;                             \
+    case 96: CALL(96); break;                             \
     case 128: CALL(128); break;                           \
+    case 192: CALL(192); break;                           \
     case 256: CALL(256); break;                           \
+    case 384: CALL(384); break;                           \
     case 512: CALL(512); break;                           \
     case 1024: CALL(1024); break;                         \
     case 2048: CALL(2048); break;                         \
     default: throw Error{CUBE_E_INVALID, "unsupported FFT size"}; \
   }
 
-template <int N>
-constexpr int col_bx() { return ColCfg<N>::BX; }
 
 }  // namespace
 
+bool fft_size_supported(int n) {
+  switch (n) {
+    case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 1024: case 2048:
+      return true;
+    default:
+      return false;
+  }
+}
+
 void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
   pl.n = n;
-#define CUBE_BX(N) pl.bx = col_bx<N>()
-  CUBE_FFT_DISPATCH(n, CUBE_BX)
-#undef CUBE_BX
+  pl.bx = col_bx_pitch(n);
+  pl.colbx = col_bx_default(n);
   pl.pitch_c = n / 2 + pl.bx;
   std::vector<float2> tw(n);
   std::vector<float> k2(n);
@@ -456,6 +513,11 @@ void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
   pl.k2 = static_cast<float*>(s.dmalloc(sizeof(float) * n));
   CUBE_HIP(hipMemcpy(pl.tw, tw.data(), sizeof(float2) * n, hipMemcpyHostToDevice));
   CUBE_HIP(hipMemcpy(pl.k2, k2.data(), sizeof(float) * n, hipMemcpyHostToDevice));
+}
+
+std::vector<int> fft_col_widths(int n) {
+  if (n >= 1024) return {8};
+  return {8, 16};
 }
 
 void fft_plan_destroy(Sim& s, FFTPlan& pl) {

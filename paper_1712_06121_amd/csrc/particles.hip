@@ -229,7 +229,20 @@ struct MoveArgs {
   int64_t lat_pitch_f;
   int np, q;
   float vfac, lunit;
+  // device-side schedule (replayable step graphs): when kd is set, the kick and drift factors of
+  // step j = *kstep are kd[2 j] and kd[2 j + 1] instead of kf and df
+  const float* kd;
+  const int* kstep;
 };
+
+// the kick/drift factors of this launch
+__device__ __forceinline__ void resolve_factors(MoveArgs& a) {
+  if (a.kd) {
+    const int j = *a.kstep;
+    a.kf = a.kd[2 * j];
+    a.df = a.kd[2 * j + 1];
+  }
+}
 
 struct Moved {
   float v[3];
@@ -453,6 +466,7 @@ struct MoveLds {
 
 template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
 __global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
+  resolve_factors(a);
   __shared__ float ph[MoveLds<MODE, PRE>::kPh];
   __shared__ float gd[MoveLds<MODE, PRE>::kGd];
   __shared__ uint32_t mcnt[TC * 27];
@@ -547,6 +561,7 @@ __device__ __forceinline__ int encode_nu(float u, const float* edges, const int1
 
 template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
 __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
+  resolve_factors(a);
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
   __shared__ float ph[MoveLds<MODE, PRE>::kPh];
@@ -657,6 +672,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 template <int NCHI, int NNU, bool SCATTER>
 __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
+  resolve_factors(a);
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
   constexpr int NTH = 1024;
@@ -1212,8 +1228,17 @@ static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipS
   CUBE_HIP(hipGetLastError());
 }
 
+__global__ void k_advance_step(int* step) {
+  if (threadIdx.x == 0) step[0] += 1;
+}
+
+void launch_advance_step(Sim& s, hipStream_t st) {
+  k_advance_step<<<1, 64, 0, st>>>(s.step_dev);
+  CUBE_HIP(hipGetLastError());
+}
+
 void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
-                 hipEvent_t* evs) {
+                 hipEvent_t* evs, bool dev_sched) {
   const int nxt = s.cur ^ 1;
   MoveArgs a{};
   a.chi = s.chi[s.cur];
@@ -1245,6 +1270,8 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   a.slot = s.slot;
   a.mom = s.mom;
   a.flags = s.flags;
+  a.kd = dev_sched ? s.sched_dev : nullptr;
+  a.kstep = dev_sched ? s.step_dev : nullptr;
   if (mode == 2) {
     a.psi0 = psi[0];
     a.psi1 = psi[1];
@@ -1257,7 +1284,7 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   }
   const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
   // precomputed gradient tile when particles are at least half as many as fine cells
-  const bool pre = mode == 0 && 2 * s.n >= (int64_t)s.nm * s.nm * s.nm;
+  const bool pre = mode == 0 && (s.move_variant < 0 ? 2 * s.n >= (int64_t)s.nm * s.nm * s.nm : s.move_variant == 1);
 #define CUBE_COUNT(X, V)                                                                        \
   do {                                                                                          \
     if (mode == 0 && pre) k_move_dense<X, V, false><<<grid, 1024, 0, st>>>(a);                   \

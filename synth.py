@@ -33,6 +33,41 @@ WORKLOADS = {
 }
 
 
+def ensemble(seed: int = 4, nbox: int = 64, n_steps: int = 50) -> list[dict]:
+    """Ensemble of independent boxes: particles per side drawn from {64, 96, 128, 192, 256}, a fine
+    mesh of twice that per side, coarse cells a quarter of the mesh, 1.5625 Mpc/h per particle
+    spacing, flat LCDM (Omega_m 0.3, h 0.7) with n_s ~ U[0.9, 1.0] and sigma8 ~ U[0.7, 0.9], 1-byte
+    codes, Zel'dovich ICs at a = 0.02 with a seed per box, n_steps steps uniform in a to a = 1."""
+    g = rng(seed)
+    sides = g.choice([64, 96, 128, 192, 256], size=nbox)
+    out = []
+    for i, n in enumerate(sides):
+        n = int(n)
+        out.append(dict(np_side=n, nm_side=2 * n, nc_side=n // 2, box=1.5625 * n, x_bytes=1, v_bytes=1,
+                        omega_m=0.3, omega_l=0.7, h=0.7, sigma8=float(g.uniform(0.7, 0.9)),
+                        n_s=float(g.uniform(0.9, 1.0)), a_init=0.02, a_final=1.0, n_steps=n_steps, spacing=1,
+                        seed=1000 + 17 * seed + i))
+    return out
+
+
+def serving_jobs(seed: int = 5, n: int = 2000, rate: float = 20.0, n_steps: int = 50) -> list[dict]:
+    """A Poisson stream of simulation requests: exponential gaps of mean 1/rate seconds; particles
+    per side 64, 128 or 256 with probabilities 0.5, 0.35, 0.15; mesh twice and coarse cells half the
+    particle count per side, 1.5625 Mpc/h per particle spacing; flat LCDM with sigma8 ~ U[0.7, 0.9];
+    1-byte codes; n_steps steps to a = 1. Each item: dict(arrival=seconds, cfg=simulation parameters)."""
+    g = rng(seed)
+    t = np.cumsum(g.exponential(1.0 / rate, size=n))
+    sides = g.choice([64, 128, 256], size=n, p=[0.5, 0.35, 0.15])
+    out = []
+    for i in range(n):
+        side = int(sides[i])
+        cfg = dict(np_side=side, nm_side=2 * side, nc_side=side // 2, box=1.5625 * side, x_bytes=1, v_bytes=1,
+                   omega_m=0.3, omega_l=0.7, h=0.7, sigma8=float(g.uniform(0.7, 0.9)), n_s=1.0, a_init=0.02,
+                   a_final=1.0, n_steps=n_steps, spacing=1, seed=50000 + i)
+        out.append(dict(arrival=float(t[i]), cfg=cfg))
+    return out
+
+
 def rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 

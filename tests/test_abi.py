@@ -36,3 +36,18 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(CubeParams) == 8 * 4 + 8 * 8 + 8 + 8
     assert CubeParams.box.offset == 32 and CubeParams.seed.offset == 96
     assert ctypes.sizeof(CubeStateView) == 5 * 8 + 8 + 8 + 8
+
+
+def test_footprint_is_host_arithmetic():
+    """cube_footprint needs no device: it grows with the box and, at 2048^3 with 1-byte codes, is
+    the resident state (180.1 GB: two particle buffers, coarse-cell arrays, the padded mesh) plus
+    the two initial-condition displacement fields that do not fit in a particle buffer."""
+    from paper_1712_06121_amd import footprint
+    import synth
+    c3 = synth.WORKLOADS["c3_pm2048"]
+    fp = footprint(**c3)
+    field = 2048 * 2048 * (1024 + 8) * 8
+    resident = fp - 2 * field - 4 * (3 * 1024 * 1024 + 1)
+    assert abs(resident / 180.1e9 - 1) < 1e-3
+    sizes = [footprint(**dict(c3, np_side=n, nm_side=n, nc_side=n // 4)) for n in (64, 128, 256, 512)]
+    assert all(a < b for a, b in zip(sizes, sizes[1:]))

@@ -1,0 +1,101 @@
+"""Ensembles of boxes stepped together (cube_batch_*) and the equivalent kernel variants.
+
+Every box of a batch must evolve exactly as it does alone, whatever kernel variants the
+autotuner picks: states are compared bit for bit."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("cnt", "chi", "nu", "vc", "vs")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1712_06121_amd as m
+    return m
+
+
+def small_ensemble():
+    base = dict(omega_m=0.3, omega_l=0.7, h=0.7, a_init=0.02, a_final=1.0, n_steps=12, spacing=1, x_bytes=1,
+                v_bytes=1)
+    return [
+        dict(base, np_side=32, nm_side=64, box=50.0, sigma8=0.8, n_s=0.95, seed=11),
+        dict(base, np_side=48, nm_side=96, box=75.0, sigma8=0.75, n_s=0.92, seed=12),
+        dict(base, np_side=64, nm_side=128, box=100.0, sigma8=0.85, n_s=0.99, seed=13),
+        dict(base, np_side=32, nm_side=64, box=50.0, sigma8=0.7, n_s=0.9, seed=14, x_bytes=2),
+    ]
+
+
+def run_alone(lib, cfg, k, variant=None):
+    with lib.Sim(**cfg) as s:
+        s.init_ic()
+        if variant is not None:
+            s.set_variant(*variant)
+        s.step(k)
+        return s.get_state()
+
+
+def assert_same(a, b, what):
+    for key in KEYS:
+        assert np.array_equal(a[key], b[key]), f"{what}: {key}"
+
+
+def test_batch_equals_each_box_alone(lib):
+    cfgs = small_ensemble()
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        b.step(3)
+        b.step(4)  # two calls: the graph for each state parity, the device step counter re-synced
+        got = [box.get_state() for box in b.boxes]
+        assert all(box.steps_done == 7 for box in b.boxes)
+    for i, cfg in enumerate(cfgs):
+        assert_same(got[i], run_alone(lib, cfg, 7), f"box {i}")
+
+
+def test_batch_autotune_keeps_results(lib):
+    cfgs = small_ensemble()[:3]
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        b.step(2)
+        b.autotune()
+        variants = [box.variant for box in b.boxes]
+        b.step(3)
+        got = [box.get_state() for box in b.boxes]
+    print("variants", variants)
+    for i, cfg in enumerate(cfgs):
+        assert_same(got[i], run_alone(lib, cfg, 5), f"box {i}")
+
+
+@pytest.mark.parametrize("variant", [(0, 8), (1, 8), (0, 16), (1, 16)])
+def test_variants_are_bit_identical(lib, variant):
+    cfg = dict(synth.WORKLOADS["c1_pm32"], n_steps=12)
+    ref = run_alone(lib, cfg, 6)
+    assert_same(run_alone(lib, cfg, 6, variant), ref, f"variant {variant}")
+
+
+def test_batch_runs_to_the_end(lib):
+    # steps fine enough that no particle crosses more than one coarse cell per step
+    cfgs = [dict(c, n_steps=40) for c in small_ensemble()[:2]]
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        assert b.step(30) == lib.CUBE_OK
+        assert b.step(15) == lib.CUBE_DONE
+        assert all(box.steps_done == 40 and box.a == pytest.approx(1.0) for box in b.boxes)
+        k, pk, nmodes = b.boxes[1].get_power()
+        assert np.all(np.isfinite(pk)) and pk[0] > 0
+
+
+def test_batch_refuses_boxes_out_of_step(lib):
+    cfgs = small_ensemble()[:2]
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        b.boxes[0].step(1)  # a box stepped alone leaves the batch out of step
+        with pytest.raises(lib.CubeError) as e:
+            b.step(1)
+        assert "same step" in str(e.value)

@@ -41,7 +41,7 @@ def test_load_bit_exact(Sim, nchi, nnu, mode):
     nm, nc, n = 64, 16, 30011
     x, v = synth.particle_cloud(21 + nchi + 2 * nnu, n, nm)
     ref = twin.load(x, v, nc, nchi, nnu, mode)
-    with Sim(32, nm, 100.0, x_bytes=nchi, v_bytes=nnu, sigma_mode=mode, capacity=n) as sim:
+    with Sim(np_for(nm), nm, 100.0, x_bytes=nchi, v_bytes=nnu, sigma_mode=mode, capacity=n) as sim:
         sim.load_particles(x, v)
         assert_state_equal(sim.get_state(), ref, f"load x{nchi}v{nnu}")
 
@@ -54,14 +54,19 @@ def test_tables_match(Sim):
         assert np.array_equal(edg, twin.edge_table(nnu))
 
 
+def np_for(nm):
+    """Smallest valid lattice side for a mesh: an FFT size, at least 32, a multiple of nm / 4."""
+    return next(p for p in (32, 48, 64, 96, 128, 192, 256) if p % (nm // 4) == 0)
+
+
 @pytest.mark.parametrize("nchi", [1, 2])
-@pytest.mark.parametrize("nm", [32, 64, 128])
+@pytest.mark.parametrize("nm", [32, 64, 96, 128])
 def test_deposit_bit_exact(Sim, nchi, nm):
     nc = nm // 4
     n = 5 * nm**3 // 16 + 7
     x, v = synth.particle_cloud(31 + nm, n, nm, clump_frac=0.4)
     ref = twin.load(x, v, nc, nchi, 1)
-    with Sim(32 if nm < 128 else 32, nm, 100.0, x_bytes=nchi, capacity=n) as sim:
+    with Sim(np_for(nm), nm, 100.0, x_bytes=nchi, capacity=n) as sim:
         sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
         sim.stage_deposit()
         got = sim.get_mesh()
@@ -69,12 +74,12 @@ def test_deposit_bit_exact(Sim, nchi, nm):
     assert np.array_equal(got, exp)
 
 
-@pytest.mark.parametrize("nm", [32, 64, 256])
+@pytest.mark.parametrize("nm", [32, 64, 96, 192, 256])
 def test_solve_within_tolerance(Sim, nm):
     nc = nm // 4
     rng = np.random.default_rng(nm)
     delta = rng.normal(size=(nm, nm, nm)).astype(np.float32)
-    with Sim(32 if nm < 256 else 64, nm, 100.0, omega_m=0.3) as sim:
+    with Sim(np_for(nm), nm, 100.0, omega_m=0.3) as sim:
         sim.set_mesh(delta)
         sim.stage_solve()
         phi = sim.get_mesh()
@@ -111,6 +116,9 @@ MOVE_CASES = [
     (1, 1, 1, 32, 20000, 1.0),
     (2, 1, 0, 64, 160000, 1.0),
     (1, 1, 1, 64, 300000, 0.7),
+    # a 3 * 2^k mesh (radix-3 FFT sizes), generic and dense paths
+    (1, 1, 1, 96, 200000, 0.7),
+    (1, 1, 1, 96, 460000, 0.7),
 ]
 
 
@@ -125,7 +133,7 @@ def test_move_bit_exact(Sim, nchi, nnu, mode, nm, n, vscale):
     assert not info["cfl"]
     moved = (info["dcode"] != 13).mean()
     assert moved > 0.02  # many particles change cell, some cross the periodic boundary
-    with Sim(32, nm, 100.0, x_bytes=nchi, v_bytes=nnu, sigma_mode=mode, capacity=n) as sim:
+    with Sim(np_for(nm), nm, 100.0, x_bytes=nchi, v_bytes=nnu, sigma_mode=mode, capacity=n) as sim:
         sim.set_state(st.cnt, st.chi, st.nu, st.vc, st.vs)
         sim.set_mesh(phi)
         sim.stage_move(kf, df)

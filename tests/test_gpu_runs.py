@@ -32,7 +32,8 @@ def twin_state(d, cfg):
     return twin.State(cfg["nc_side"], cfg["x_bytes"], cfg["v_bytes"], d["cnt"], d["chi"], d["nu"], d["vc"], d["vs"])
 
 
-@pytest.mark.parametrize("name,np_side,nm", [("c1_pm32", 32, 64), ("c2_pm128", 64, 128), ("c3_sibling256", 64, 64)])
+@pytest.mark.parametrize("name,np_side,nm", [("c1_pm32", 32, 64), ("c2_pm128", 64, 128), ("c3_sibling256", 64, 64),
+                                             ("c1_pm32", 48, 96), ("c2_pm128", 96, 192)])
 def test_ic_displacement_matches_oracle(Sim, name, np_side, nm):
     cfg = dict(synth.WORKLOADS[name], np_side=np_side, nm_side=nm, nc_side=nm // 4)
     with Sim(**cfg) as sim:
