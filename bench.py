@@ -124,7 +124,7 @@ def bench_ensemble(args) -> dict:
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     ref0 = b.boxes[0].get_state()
-    variants = sorted({(c["np_side"], box.variant) for c, box in zip(cfgs, b.boxes)})
+    variants = sorted({(c["np_side"], tuple(box.variant.values())) for c, box in zip(cfgs, b.boxes)})
     dev_bytes = sum(box.device_bytes for box in b.boxes)
     b.close()
     print(f"[bench] batch: {args.steps} steps in {t_batch:.3f} s, variants {variants}", file=sys.stderr, flush=True)
@@ -262,6 +262,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample-side", type=int, default=128)
     ap.add_argument("--cpu-sample-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel variants instead of timing the equivalent ones after warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy (torch.neg) over 1 GiB, the reference reading that "
                          "calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters")
@@ -304,6 +306,11 @@ def main() -> int:
         sim.step(args.warmup)
     torch.cuda.synchronize()
     print(f"[bench] {args.warmup} warmup steps done", file=sys.stderr, flush=True)
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        sim.autotune()  # bit-identical variants; the fastest of each stage on this state
+        torch.cuda.synchronize()
+        print(f"[bench] autotune in {time.perf_counter() - t0:.1f} s: {sim.variant}", file=sys.stderr, flush=True)
 
     sim.set_profiling(True)
     torch.cuda.synchronize()
@@ -353,6 +360,7 @@ def main() -> int:
             "x_bytes": cfg["x_bytes"],
             "v_bytes": cfg["v_bytes"],
             "sigma": "per-cell",
+            "variants": sim.variant,
         },
         "roofline": {
             "bound": "hbm",

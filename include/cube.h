@@ -181,18 +181,28 @@ int cube_set_profiling(cube_sim* sim, int enable);
 int cube_get_timings(const cube_sim* sim, double* ms9);
 
 /* ---- kernel variants and the autotuner ------------------------------------------------------
- * Some stages have equivalent kernel variants that give bit-identical results: the move passes
- * (move_variant 0: the 4-point gradient evaluated per CIC corner, 512-thread workgroups; 1: the
- * gradient of the whole tile precomputed in LDS, one coarse cell per wavefront, 1024-thread
- * workgroups; -1: chosen by particle density, the default) and the column width of the FFT's
- * y/z passes (fft_col_width 8 or 16 complex values; 16 only for nm_side <= 512). */
-/* Time the variants on the current state (one deposit + solve, then moves whose result is
- * discarded) and keep the fastest. The particle state is unchanged; the mesh afterwards holds the
- * potential of the current state. Errors: CUBE_E_STATE (no particles). */
+ * Some stages have equivalent kernel variants that give bit-identical results: the layout of the
+ * work, never the arithmetic, differs. */
+typedef struct {
+  int32_t move_variant;    /* 0 (default): 4-point gradient per CIC corner, 512-thread workgroups;
+                              1: gradient of the whole tile precomputed in LDS, one coarse cell per
+                              wavefront, 1024-thread workgroups; -1: 1 when there are at least half
+                              as many particles as fine cells, else 0 */
+  int32_t fft_col_width;   /* complex columns per workgroup in the y/z passes: 8 or 16 for
+                              nm_side <= 512, 4 or 8 above */
+  int32_t fft_z_order;     /* workgroup order of the z passes: 0 dispatch order, 1 contiguous ranges
+                              per XCD */
+  int32_t deposit_variant; /* bit 0: particles of a layer visited with a stride of 1/64 of the layer
+                              (lanes of a wavefront in different cells); bit 1: 512-thread
+                              workgroups instead of 256; default 3 */
+} cube_variant;
+/* Time the variants on the current state (deposits, solves, then moves whose result is
+ * discarded) and keep the fastest of each stage. The particle state is unchanged; the mesh
+ * afterwards holds the potential of the current state. Errors: CUBE_E_STATE (no particles). */
 int cube_autotune(cube_sim* sim);
-int cube_get_variant(const cube_sim* sim, int32_t* move_variant, int32_t* fft_col_width);
-/* Set the variants by hand (fft_col_width 0 keeps the current width). Errors: CUBE_E_INVALID. */
-int cube_set_variant(cube_sim* sim, int32_t move_variant, int32_t fft_col_width);
+int cube_get_variant(const cube_sim* sim, cube_variant* out);
+/* Errors: CUBE_E_INVALID for a value outside the ranges above (nothing is changed then). */
+int cube_set_variant(cube_sim* sim, const cube_variant* v);
 
 /* ---- ensembles of independent boxes ----------------------------------------------------------
  * A batch holds nbox simulations (box i created from params[i]; sizes, codecs and cosmologies may

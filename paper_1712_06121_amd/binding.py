@@ -49,6 +49,11 @@ class CubeParams(Structure):
                 ("seed", c_uint64), ("capacity", c_int64)]
 
 
+class CubeVariant(Structure):
+    _fields_ = [("move_variant", c_int32), ("fft_col_width", c_int32), ("fft_z_order", c_int32),
+                ("deposit_variant", c_int32)]
+
+
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
 FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
 
@@ -111,8 +116,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_set_profiling.argtypes = [sim_p, c_int]
     lib.cube_get_timings.argtypes = [sim_p, c_void_p]
     lib.cube_autotune.argtypes = [sim_p]
-    lib.cube_get_variant.argtypes = [sim_p, POINTER(c_int32), POINTER(c_int32)]
-    lib.cube_set_variant.argtypes = [sim_p, c_int32, c_int32]
+    lib.cube_get_variant.argtypes = [sim_p, POINTER(CubeVariant)]
+    lib.cube_set_variant.argtypes = [sim_p, POINTER(CubeVariant)]
     batch_p = c_void_p
     lib.cube_batch_create.argtypes = [POINTER(CubeParams), c_int32, c_void_p, POINTER(CubeAllocator), POINTER(c_void_p)]
     lib.cube_batch_destroy.argtypes = [batch_p]
@@ -365,14 +370,21 @@ class Sim:
         self._check(self._lib.cube_autotune(self._h))
 
     @property
-    def variant(self) -> tuple[int, int]:
-        """(move_variant, fft_col_width): -1 = by density, 0 = per-corner gradient, 1 = gradient tile."""
-        mv, bx = c_int32(), c_int32()
-        self._check(self._lib.cube_get_variant(self._h, byref(mv), byref(bx)))
-        return mv.value, bx.value
+    def variant(self) -> dict:
+        """The kernel variants in use (``cube_variant``): move_variant, fft_col_width, fft_z_order,
+        deposit_variant."""
+        v = CubeVariant()
+        self._check(self._lib.cube_get_variant(self._h, byref(v)))
+        return {name: getattr(v, name) for name, _ in CubeVariant._fields_}
 
-    def set_variant(self, move_variant: int, fft_col_width: int = 0):
-        self._check(self._lib.cube_set_variant(self._h, move_variant, fft_col_width))
+    def set_variant(self, **changes):
+        """Change some of the variants (keyword arguments named as the fields of ``variant``)."""
+        cur = self.variant
+        unknown = set(changes) - set(cur)
+        if unknown:
+            raise TypeError(f"unknown variant fields {sorted(unknown)}")
+        cur.update(changes)
+        self._check(self._lib.cube_set_variant(self._h, byref(CubeVariant(**cur))))
 
 
 class Batch:

@@ -93,34 +93,55 @@ float elapsed_ms(hipEvent_t a, hipEvent_t z) {
   return ms;
 }
 
-// Time the equivalent variants of the FFT column passes and of the move passes on the current
-// state and keep the fastest. The particle state is left unchanged (timed moves write only the
-// next-state buffers and scratch, and the parity is restored); the mesh is left holding the
-// potential of the current state.
+// Time the equivalent variants of the deposit, of the FFT column passes and of the move passes on
+// the current state and keep the fastest of each. The particle state is left unchanged (timed
+// moves write only the next-state buffers and scratch, and the parity is restored); the mesh is
+// left holding the potential of the current state.
 void autotune_sim(Sim& s) {
   require_particles(s);
   hipEvent_t e0 = s.ev[14], e1 = s.ev[15];
   constexpr int reps = 2;
-  // FFT column width
-  int best_bx = s.mesh_plan.colbx;
-  float best = 1e30f;
-  for (int bx : fft_col_widths(s.nm)) {
-    s.mesh_plan.colbx = bx;
+  auto timed = [&](auto&& fn) {
     float t = 0.f;
     for (int r = 0; r <= reps; ++r) {
-      launch_deposit(s, s.stream);
       CUBE_HIP(hipEventRecord(e0, s.stream));
-      fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+      fn();
       CUBE_HIP(hipEventRecord(e1, s.stream));
       const float ms = elapsed_ms(e0, e1);
       if (r > 0) t += ms;  // the first run warms up
     }
+    return t;
+  };
+  // deposit: particle order and workgroup size
+  int best_d = s.deposit_variant;
+  float best = 1e30f;
+  for (int v = 0; v < 4; ++v) {
+    s.deposit_variant = v;
+    const float t = timed([&] { launch_deposit(s, s.stream); });
     if (t < best) {
       best = t;
-      best_bx = bx;
+      best_d = v;
+    }
+  }
+  s.deposit_variant = best_d;
+  // FFT column width and z-pass workgroup order
+  int best_bx = s.mesh_plan.colbx, best_z = s.mesh_plan.zorder;
+  best = 1e30f;
+  for (int bx : fft_col_widths(s.nm)) {
+    for (int z = 0; z <= 1; ++z) {
+      s.mesh_plan.colbx = bx;
+      s.mesh_plan.zorder = z;
+      launch_deposit(s, s.stream);
+      const float t = timed([&] { fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr); });
+      if (t < best) {
+        best = t;
+        best_bx = bx;
+        best_z = z;
+      }
     }
   }
   s.mesh_plan.colbx = best_bx;
+  s.mesh_plan.zorder = best_z;
   launch_deposit(s, s.stream);
   fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
   // move passes: per-corner gradient vs precomputed gradient tile, with this step's factors
@@ -130,16 +151,11 @@ void autotune_sim(Sim& s) {
   best = 1e30f;
   for (int v = 0; v <= 1; ++v) {
     s.move_variant = v;
-    float t = 0.f;
-    for (int r = 0; r <= reps; ++r) {
+    const float t = timed([&] {
       const int cur = s.cur;
-      CUBE_HIP(hipEventRecord(e0, s.stream));
       launch_move(s, 0, kf, df, nullptr, 0.0f, s.stream, nullptr);
-      CUBE_HIP(hipEventRecord(e1, s.stream));
       s.cur = cur;  // discard the result
-      const float ms = elapsed_ms(e0, e1);
-      if (r > 0) t += ms;
-    }
+    });
     if (t < best) {
       best = t;
       best_v = v;
@@ -172,29 +188,34 @@ int cube_autotune(cube_sim* sim) {
   return CUBE_OK;
 }
 
-int cube_get_variant(const cube_sim* sim, int32_t* move_variant, int32_t* fft_col_width) {
-  if (!sim) return CUBE_E_INVALID;
-  if (move_variant) *move_variant = sim->s.move_variant;
-  if (fft_col_width) *fft_col_width = sim->s.mesh_plan.colbx;
+int cube_get_variant(const cube_sim* sim, cube_variant* out) {
+  if (!sim || !out) return CUBE_E_INVALID;
+  const cube::Sim& s = sim->s;
+  out->move_variant = s.move_variant;
+  out->fft_col_width = s.mesh_plan.colbx;
+  out->fft_z_order = s.mesh_plan.zorder;
+  out->deposit_variant = s.deposit_variant;
   return CUBE_OK;
 }
 
-int cube_set_variant(cube_sim* sim, int32_t move_variant, int32_t fft_col_width) {
-  if (!sim) return CUBE_E_INVALID;
+int cube_set_variant(cube_sim* sim, const cube_variant* v) {
+  if (!sim || !v) return CUBE_E_INVALID;
   cube::Sim& s = sim->s;
-  if (move_variant < -1 || move_variant > 1) {
-    s.last_error = "move_variant must be -1, 0 or 1";
+  const std::vector<int> ok = cube::fft_col_widths(s.nm);
+  std::string err;
+  if (v->move_variant < -1 || v->move_variant > 1) err = "move_variant must be -1, 0 or 1";
+  else if (std::find(ok.begin(), ok.end(), v->fft_col_width) == ok.end())
+    err = "unsupported FFT column width for this mesh size";
+  else if (v->fft_z_order < 0 || v->fft_z_order > 1) err = "fft_z_order must be 0 or 1";
+  else if (v->deposit_variant < 0 || v->deposit_variant > 3) err = "deposit_variant must be in 0..3";
+  if (!err.empty()) {
+    s.last_error = err;
     return CUBE_E_INVALID;
   }
-  if (fft_col_width != 0) {
-    const std::vector<int> ok = cube::fft_col_widths(s.nm);
-    if (std::find(ok.begin(), ok.end(), fft_col_width) == ok.end()) {
-      s.last_error = "unsupported FFT column width for this mesh size";
-      return CUBE_E_INVALID;
-    }
-    s.mesh_plan.colbx = fft_col_width;
-  }
-  s.move_variant = move_variant;
+  s.move_variant = v->move_variant;
+  s.mesh_plan.colbx = v->fft_col_width;
+  s.mesh_plan.zorder = v->fft_z_order;
+  s.deposit_variant = v->deposit_variant;
   return CUBE_OK;
 }
 
@@ -281,7 +302,7 @@ int cube_batch_init_ic(cube_batch* b) {
 int cube_batch_autotune(cube_batch* b) {
   if (!b) return CUBE_E_INVALID;
   // one measurement per distinct box shape, applied to every box of that shape
-  std::map<std::tuple<int, int, int, int>, std::pair<int, int>> chosen;
+  std::map<std::tuple<int, int, int, int>, cube_variant> chosen;
   for (size_t i = 0; i < b->boxes.size(); ++i) {
     cube::Sim& s = b->boxes[i]->s;
     const auto key = std::make_tuple(s.nm, s.np, s.nchi, s.nnu);
@@ -292,10 +313,11 @@ int cube_batch_autotune(cube_batch* b) {
         b->last_error = "box " + std::to_string(i) + ": " + cube_last_error(b->boxes[i]);
         return rc;
       }
-      chosen[key] = {s.move_variant, s.mesh_plan.colbx};
+      cube_variant v;
+      cube_get_variant(b->boxes[i], &v);
+      chosen[key] = v;
     } else {
-      s.move_variant = it->second.first;
-      s.mesh_plan.colbx = it->second.second;
+      cube_set_variant(b->boxes[i], &it->second);
     }
   }
   cube::destroy_graphs(*b);  // the captured kernels depend on the variants

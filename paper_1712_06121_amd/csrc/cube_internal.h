@@ -33,6 +33,17 @@ enum : uint32_t {
   FLAG_COUNT = 8u,      // total count after the move differs from N
 };
 
+// ---- XCD-aware workgroup order ----------------------------------------------------------------
+// The dispatcher hands workgroups of a launch to the 8 XCDs in turn (workgroup b to XCD b % 8),
+// and each XCD has its own L2. Mapping the b-th dispatched workgroup to logical block
+// (b % 8) * n/8 + b / 8 (with the remainder spread over the first XCDs) gives every XCD one
+// contiguous range of logical blocks, so neighbouring blocks -- which share cache lines, halos
+// and DRAM pages -- run on the same XCD at about the same time. It is a bijection for any n.
+__host__ __device__ inline unsigned xcd_block(unsigned b, unsigned n) {
+  const unsigned per = n / 8, rem = n % 8, x = b % 8, i = b / 8;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
 // ---- FFT plan: one cubic size N, half-complex padded layout --------------------------------
 // Real-space field: N x N rows of `pitch_c * 2` floats (x fastest, N used). Fourier space:
 // the same rows hold pitch_c complex values, x-frequencies 0..N/2 (Nyquist at index N/2);
@@ -40,7 +51,8 @@ enum : uint32_t {
 struct FFTPlan {
   int n = 0;
   int bx = 0;        // row padding (complex values): the widest column block of the y/z passes
-  int colbx = 0;     // column block width used by the y/z passes (8 or 16; tunable)
+  int colbx = 0;     // column block width used by the y/z passes (tunable)
+  int zorder = 0;    // workgroup order of the z passes: 0 dispatch order, 1 XCD-contiguous (tunable)
   int pitch_c = 0;   // complex values per row, = n/2 + bx
   float2* tw = nullptr;    // exp(-2 pi i t / n), t = 0..n-1 (device)
   float* k2 = nullptr;     // (2 pi f(t) / n)^2 with f the signed frequency of index t (device)
@@ -106,7 +118,8 @@ struct Sim {
   int* step_dev = nullptr;     // step index read by graph-replayed move kernels (device)
   int steps_done = 0;
   bool half_drift_done = false;
-  int move_variant = -1;  // move passes: -1 by particle density, 0 per-corner gradient, 1 gradient tile
+  int move_variant = 0;     // move passes: -1 by particle density, 0 per-corner gradient, 1 gradient tile
+  int deposit_variant = 3;  // bit 0: interleaved particle order, bit 1: 512-thread workgroups
   double a_now = 0.0;
   bool have_particles = false;
 

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
                                                   const float2* __restrict__ tw) {
   constexpr int H = RowCfg<N>::H, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
   __shared__ float2 lds[NL * H];
-  const int64_t row0 = (int64_t)blockIdx.x * NL;
+  const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NL;
   constexpr int F4 = N / 4;
   constexpr int LPT = (NL * F4 + BLOCK - 1) / BLOCK;
   float4 stage[LPT];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
   constexpr int H = N / 2, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
   constexpr int LS = H + 1;
   __shared__ float2 lds[NL * LS];
-  const int64_t row0 = (int64_t)blockIdx.x * NL;
+  const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NL;
   constexpr int LPT = (NL * LS + BLOCK - 1) / BLOCK;
   float2 stage[LPT];
 #pragma unroll
@@ -269,8 +269,8 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
 }
 
 // ---- y / z passes: blocks of BX columns ------------------------------------------------------
-// BX: complex columns per workgroup (8 or 16; 16 needs N <= 512 to fit LDS). The pitch of the
-// padded rows always leaves room for 16.
+// BX: complex columns per workgroup (4 or 8 for N >= 1024, 8 or 16 below: 16 needs N <= 512 to
+// fit LDS). The padding of the rows leaves room for the widest.
 template <int N, int BX>
 struct ColCfg {
   static constexpr int NQ = N * BX / 2;
@@ -288,6 +288,7 @@ struct ColArgs {
   const float* tab;  // initial-condition factor per |n|^2
   int dim;           // initial-condition component
   int half;          // N / 2
+  int order;         // workgroup order: 0 dispatch order, 1 XCD-contiguous ranges
 };
 
 __device__ __forceinline__ int signed_freq(int t, int n) { return t <= n / 2 ? t : t - n; }
@@ -298,7 +299,9 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
                                                                  const float2* __restrict__ tw, ColArgs a) {
   constexpr int BLOCK = ColCfg<N, BX>::BLOCK;
   __shared__ float2 lds[N * BX];
-  const int cb = blockIdx.x, o = blockIdx.y;
+  const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
+  const unsigned lb = a.order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
+  const int cb = lb % gridDim.x, o = lb / gridDim.x;
   const int64_t base = (int64_t)o * ostride + (int64_t)cb * BX;
   constexpr int Q = BX / 2;
   // every load of the block in flight at once (registers), then into LDS
@@ -416,10 +419,19 @@ void run_col_bx(const FFTPlan& pl, const float* src, float* dst, int axis, const
 }
 
 template <int N, int MODE>
-void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
+void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a0, hipStream_t st) {
+  ColArgs a = a0;
+  // y passes: XCD-contiguous ranges share the 128-byte lines of neighbouring column blocks in one
+  // L2; z passes: tunable
+  a.order = axis == 1 ? 1 : pl.zorder;
   if constexpr (N < 1024) {
     if (pl.colbx == 16) {
       run_col_bx<N, MODE, 16>(pl, src, dst, axis, a, st);
+      return;
+    }
+  } else {
+    if (pl.colbx == 4) {
+      run_col_bx<N, MODE, 4>(pl, src, dst, axis, a, st);
       return;
     }
   }
@@ -428,7 +440,7 @@ void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const Co
 
 template <int N>
 void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st, hipEvent_t* ev) {
-  ColArgs a{pl.k2, gconst, nullptr, nullptr, 0, N / 2};
+  ColArgs a{pl.k2, gconst, nullptr, nullptr, 0, N / 2, 0};
   if (ev) CUBE_HIP(hipEventRecord(ev[0], st));
   run_x<N>(pl, d, true, st);
   if (ev) CUBE_HIP(hipEventRecord(ev[1], st));
@@ -444,7 +456,7 @@ void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st, hipEvent
 
 template <int N>
 void forward_n(const FFTPlan& pl, float* d, hipStream_t st) {
-  ColArgs a{pl.k2, 0.f, nullptr, nullptr, 0, N / 2};
+  ColArgs a{pl.k2, 0.f, nullptr, nullptr, 0, N / 2, 0};
   run_x<N>(pl, d, true, st);
   run_col<N, COL_FWD>(pl, d, d, 1, a, st);
   run_col<N, COL_FWD>(pl, d, d, 2, a, st);
@@ -452,7 +464,7 @@ void forward_n(const FFTPlan& pl, float* d, hipStream_t st) {
 
 template <int N>
 void power_n(const FFTPlan& pl, float* d, double* acc, hipStream_t st) {
-  ColArgs a{pl.k2, 0.f, acc, nullptr, 0, N / 2};
+  ColArgs a{pl.k2, 0.f, acc, nullptr, 0, N / 2, 0};
   run_x<N>(pl, d, true, st);
   run_col<N, COL_FWD>(pl, d, d, 1, a, st);
   run_col<N, COL_POWER>(pl, d, d, 2, a, st);
@@ -460,7 +472,7 @@ void power_n(const FFTPlan& pl, float* d, double* acc, hipStream_t st) {
 
 template <int N>
 void ic_n(const FFTPlan& pl, const float* wk, float* out, const float* tab, int dim, hipStream_t st) {
-  ColArgs a{pl.k2, 0.f, nullptr, tab, dim, N / 2};
+  ColArgs a{pl.k2, 0.f, nullptr, tab, dim, N / 2, 0};
   run_col<N, COL_PSI>(pl, wk, out, 2, a, st);
   run_col<N, COL_INV>(pl, out, out, 1, a, st);
   run_x<N>(pl, out, false, st);
@@ -498,6 +510,7 @@ void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
   pl.n = n;
   pl.bx = col_bx_pitch(n);
   pl.colbx = col_bx_default(n);
+  pl.zorder = 0;
   pl.pitch_c = n / 2 + pl.bx;
   std::vector<float2> tw(n);
   std::vector<float> k2(n);
@@ -516,7 +529,7 @@ void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
 }
 
 std::vector<int> fft_col_widths(int n) {
-  if (n >= 1024) return {8};
+  if (n >= 1024) return {4, 8};
   return {8, 16};
 }
 

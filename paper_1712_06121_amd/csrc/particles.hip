@@ -102,6 +102,7 @@ struct DepArgs {
   int nm, nc, nt;
   int zc;  // coarse layers per z chunk
   double inv_mean;
+  int interleave;  // visit a layer's particles with a stride (fewer lanes adding to one cell at once)
 };
 
 constexpr int DTX = 8;            // coarse cells per column side
@@ -117,7 +118,7 @@ __device__ __forceinline__ int slot_of(int p) { return ((p % NSLOT) + NSLOT) % N
 // reading the particles of the DR x DR cells (column + ring), and adds exact integer CIC weights
 // to a rolling set of NSLOT fine planes in LDS. After layer sz, planes up to 4 sz + 2 receive no
 // more mass: they are converted once to FP32 delta, written, and their slots reused.
-template <int NCHI>
+template <int NCHI, int BLK>
 __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   using CT = chi_t<NCHI>;
   constexpr int SH = 8 * NCHI - 1;
@@ -125,8 +126,10 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   __shared__ uint32_t pre[DRC + 1];
   __shared__ uint64_t start[DRC];
   __shared__ uint32_t wsum[BLK / 64];
-  const int cx0 = (blockIdx.x % a.nt) * DTX, cy0 = (blockIdx.x / a.nt) * DTX;
-  const int cz0 = blockIdx.y * a.zc;
+  const unsigned lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const unsigned bxy = lb % gridDim.x, bz = lb / gridDim.x;
+  const int cx0 = (bxy % a.nt) * DTX, cy0 = (bxy / a.nt) * DTX;
+  const int cz0 = bz * a.zc;
   const int cz1 = min(cz0 + a.zc, a.nc);
   const int pz0 = 4 * cz0, pz1 = 4 * cz1;  // owned fine planes [pz0, pz1)
   for (int i = threadIdx.x; i < NSLOT * DF * DF; i += BLK) rho[i] = 0ull;
@@ -142,7 +145,11 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
       start[threadIdx.x] = a.off[c];
     }
     const uint32_t total = block_exclusive_scan(cntv, pre, DRC, wsum);
-    for (uint32_t i = threadIdx.x; i < total; i += BLK) {
+    const uint32_t q64 = total / 64;
+    for (uint32_t it = threadIdx.x; it < total; it += BLK) {
+      // interleaved: lane l of the w-th group of 64 takes particle l * (total / 64) + w, so the lanes
+      // of one wavefront hold particles of different cells (a bijection on [0, 64 * (total / 64)))
+      const uint32_t i = (a.interleave && it < 64 * q64) ? (it % 64) * q64 + it / 64 : it;
       const int s = find_cell(pre, DRC, i);
       const int64_t p = (int64_t)start[s] + (i - pre[s]);
       const int sl[3] = {s % DR - 1, s / DR - 1, sz};
@@ -154,23 +161,27 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
         i0[d] = pl >> SH;
         w1[d] = pl & ((1 << SH) - 1);
       }
+      // weight products: < 2^(3 SH) -- 32-bit arithmetic for 1-byte codes, one 64-bit product else
+      const uint32_t wz2[2] = {(uint32_t)((1 << SH) - w1[2]), (uint32_t)w1[2]};
+      const uint32_t wy2[2] = {(uint32_t)((1 << SH) - w1[1]), (uint32_t)w1[1]};
+      const uint32_t wx2[2] = {(uint32_t)((1 << SH) - w1[0]), (uint32_t)w1[0]};
 #pragma unroll
       for (int dz = 0; dz < 2; ++dz) {
         const int pz = i0[2] + dz;
         if (pz < pz0 || pz >= pz1) continue;
         const int sb = slot_of(pz) * DF * DF;
-        const unsigned long long wz = dz ? (unsigned long long)w1[2] : (unsigned long long)((1 << SH) - w1[2]);
 #pragma unroll
         for (int dy = 0; dy < 2; ++dy) {
           const int y = i0[1] + dy;
           if (y < 0 || y >= DF) continue;
-          const unsigned long long wy = dy ? (unsigned long long)w1[1] : (unsigned long long)((1 << SH) - w1[1]);
+          const uint32_t wzy = wz2[dz] * wy2[dy];
 #pragma unroll
           for (int dx = 0; dx < 2; ++dx) {
             const int x = i0[0] + dx;
             if (x < 0 || x >= DF) continue;
-            const unsigned long long wx = dx ? (unsigned long long)w1[0] : (unsigned long long)((1 << SH) - w1[0]);
-            atomicAdd(&rho[sb + y * DF + x], wz * wy * wx);
+            const unsigned long long w = NCHI == 1 ? (unsigned long long)(wzy * wx2[dx])
+                                                   : (unsigned long long)wzy * (unsigned long long)wx2[dx];
+            atomicAdd(&rho[sb + y * DF + x], w);
           }
         }
       }
@@ -241,6 +252,36 @@ __device__ __forceinline__ void resolve_factors(MoveArgs& a) {
     const int j = *a.kstep;
     a.kf = a.kd[2 * j];
     a.df = a.kd[2 * j + 1];
+  }
+}
+
+// rint(x) as int64 for |x| < 2^51: adding 1.5 * 2^52 rounds x to the nearest integer (ties to
+// even, as rint does) in the low mantissa bits; the difference of the bit patterns is that integer
+__device__ __forceinline__ long long rint_ll(double x) {
+  const double magic = 6755399441055744.0;
+  return __double_as_longlong(x + magic) - __double_as_longlong(magic);
+}
+
+// fixed-point velocity moments of one particle: rint(v_d 2^32) and sum_d rint(v_d^2 2^24). The
+// second needs |v| < 2^13.5 for rint_ll; larger speeds (up to the 2^15 overflow limit) take the
+// general conversion, decided per wavefront.
+__device__ __forceinline__ void velocity_moments(const float* v, long long* q) {
+  const bool big = fabsf(v[0]) >= 8192.0f || fabsf(v[1]) >= 8192.0f || fabsf(v[2]) >= 8192.0f;
+  q[3] = 0;
+  if (__ballot(big) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double vd = (double)v[d];
+      q[d] = rint_ll(vd * 4294967296.0);
+      q[3] += rint_ll(vd * vd * 16777216.0);
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double vd = (double)v[d];
+      q[d] = rint_ll(vd * 4294967296.0);
+      q[3] += __double2ll_rn(vd * vd * 16777216.0);
+    }
   }
 }
 
@@ -462,22 +503,29 @@ template <int MODE, bool PRE>
 struct MoveLds {
   static constexpr int kPh = MODE == 0 ? PH * PH * PH : 1;
   static constexpr int kGd = (MODE == 0 && PRE) ? 3 * DG * DG * DG : 1;
+  // moments: in LDS over the tile and its ring, flushed at the end; with the potential tile in LDS
+  // (MODE 0) they go to the global accumulators directly, so that three workgroups fit a CU
+  static constexpr bool kGlobalMom = MODE == 0;
+  static constexpr int kMom = kGlobalMom ? 1 : RC * 4;
 };
 
+// at least six wavefronts per SIMD (three 512-thread workgroups per CU): at most 80 VGPRs
 template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
-__global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k_move_count(MoveArgs a) {
   resolve_factors(a);
-  __shared__ float ph[MoveLds<MODE, PRE>::kPh];
-  __shared__ float gd[MoveLds<MODE, PRE>::kGd];
+  using L = MoveLds<MODE, PRE>;
+  __shared__ float ph[L::kPh];
+  __shared__ float gd[L::kGd];
   __shared__ uint32_t mcnt[TC * 27];
-  __shared__ unsigned long long mom[RC * 4];
+  __shared__ unsigned long long mom[L::kMom];
   __shared__ uint32_t pre[TC + 1];
   __shared__ uint64_t start[TC];
   __shared__ uint32_t wsum[NTH / 64];
-  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) mcnt[i] = 0u;
-  for (int i = threadIdx.x; i < RC * 4; i += NTH) mom[i] = 0ull;
+  if constexpr (!L::kGlobalMom)
+    for (int i = threadIdx.x; i < RC * 4; i += NTH) mom[i] = 0ull;
   const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int c0, c1;
@@ -487,7 +535,8 @@ __global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
     const uint32_t i = base + lane;
     const bool active = i < p1;  // active lanes form a prefix of the wave
     int key = -1, r = 0;
-    long long q[4] = {0, 0, 0, 0};
+    long long q[4];
+    float vm[3] = {0.f, 0.f, 0.f};
     if (active) {
       const int s = find_cell_in(pre, c0, c1, i);
       const uint32_t li = i - pre[s];
@@ -496,13 +545,11 @@ __global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
       const int dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
       key = s * 27 + dcode;
       r = (s % T + 1 + m.k[0]) + RG * ((s / T) % T + 1 + m.k[1]) + RG * RG * (s / (T * T) + 1 + m.k[2]);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double vd = (double)m.v[d];
-        q[d] = __double2ll_rn(vd * 4294967296.0);
-        q[3] += __double2ll_rn(vd * vd * 16777216.0);
-      }
+      vm[0] = m.v[0];
+      vm[1] = m.v[1];
+      vm[2] = m.v[2];
     }
+    velocity_moments(vm, q);
     // sum over runs of consecutive lanes with the same (cell, displacement): most particles stay
     // in their cell, so one atomic per run replaces up to 64 conflicting ones
     const int kprev = __shfl_up(key, 1, 64);
@@ -525,8 +572,17 @@ __global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
     const bool tail = lane == 63 || knext != key;
     if (active && tail) {
       atomicAdd(&mcnt[key], (uint32_t)(lane - st + 1));
+      if constexpr (L::kGlobalMom) {
+        const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
+        const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
+        const int64_t cn = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
 #pragma unroll
-      for (int d = 0; d < 4; ++d) atomicAdd(&mom[r * 4 + d], (unsigned long long)q[d]);
+        for (int d = 0; d < 4; ++d)
+          atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
+      } else {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) atomicAdd(&mom[r * 4 + d], (unsigned long long)q[d]);
+      }
     }
   }
   __syncthreads();
@@ -535,14 +591,16 @@ __global__ __launch_bounds__(NTH) void k_move_count(MoveArgs a) {
     const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
     a.mig[d * a.nc3 + c] = mcnt[i];
   }
-  for (int i = threadIdx.x; i < RC * 4; i += NTH) {
-    const unsigned long long v = mom[i];
-    if (v == 0ull) continue;
-    const int r = i / 4, q = i % 4;
-    const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
-    const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
-    const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
-    atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[q * a.nc3 + c]), v);
+  if constexpr (!L::kGlobalMom) {
+    for (int i = threadIdx.x; i < RC * 4; i += NTH) {
+      const unsigned long long v = mom[i];
+      if (v == 0ull) continue;
+      const int r = i / 4, q = i % 4;
+      const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
+      const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
+      const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[q * a.nc3 + c]), v);
+    }
   }
 }
 
@@ -572,7 +630,7 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   __shared__ uint32_t wsum[NTH / 64];
   __shared__ float edges_lds[NNU == 1 ? 254 : 1];
   __shared__ int16_t bucket_lds[NNU == 1 ? 1024 : 1];
-  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
   const int nedge = 2 * a.vhalf;
@@ -687,7 +745,7 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
   __shared__ float tdec_lds[NNU == 1 ? 255 : 1];
   __shared__ float edges_lds[(SCATTER && NNU == 1) ? 254 : 1];
   __shared__ int16_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];
-  const TileGeom g = tile_of(blockIdx.x, a.nt);
+  const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<0, true, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
   if constexpr (!SCATTER)
@@ -806,15 +864,8 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
       }
       const int dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1);
       if constexpr (!SCATTER) {
-        long long q[4] = {0, 0, 0, 0};
-        if (active) {
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const double vd = (double)v[d];
-            q[d] = __double2ll_rn(vd * 4294967296.0);
-            q[3] += __double2ll_rn(vd * vd * 16777216.0);
-          }
-        }
+        long long q[4];
+        velocity_moments(v, q);  // inactive lanes hold v = 0
         const bool stay = active && dcode == 13;
         const unsigned long long smask = __ballot(stay);
         unsigned long long tot[4];
@@ -1190,9 +1241,15 @@ void launch_deposit(Sim& s, hipStream_t st) {
   a.zc = (s.nc + nchunk - 1) / nchunk;
   nchunk = (s.nc + a.zc - 1) / a.zc;
   a.inv_mean = (double)s.nm * (double)s.nm * (double)s.nm / ((double)s.n * ldexp(1.0, 3 * (8 * s.nchi - 1)));
+  a.interleave = s.deposit_variant & 1;
   const dim3 grid((unsigned)cols, (unsigned)nchunk);
-  if (s.nchi == 1) k_deposit<1><<<grid, BLK, 0, st>>>(a);
-  else k_deposit<2><<<grid, BLK, 0, st>>>(a);
+  if (s.deposit_variant & 2) {
+    if (s.nchi == 1) k_deposit<1, 512><<<grid, 512, 0, st>>>(a);
+    else k_deposit<2, 512><<<grid, 512, 0, st>>>(a);
+  } else {
+    if (s.nchi == 1) k_deposit<1, 256><<<grid, 256, 0, st>>>(a);
+    else k_deposit<2, 256><<<grid, 256, 0, st>>>(a);
+  }
   CUBE_HIP(hipGetLastError());
 }
 

@@ -36,7 +36,7 @@ def run_alone(lib, cfg, k, variant=None):
     with lib.Sim(**cfg) as s:
         s.init_ic()
         if variant is not None:
-            s.set_variant(*variant)
+            s.set_variant(**variant)
         s.step(k)
         return s.get_state()
 
@@ -72,11 +72,25 @@ def test_batch_autotune_keeps_results(lib):
         assert_same(got[i], run_alone(lib, cfg, 5), f"box {i}")
 
 
-@pytest.mark.parametrize("variant", [(0, 8), (1, 8), (0, 16), (1, 16)])
+VARIANTS = [dict(move_variant=0, fft_col_width=8), dict(move_variant=1, fft_col_width=8),
+            dict(move_variant=0, fft_col_width=16, fft_z_order=1), dict(move_variant=1, fft_col_width=16),
+            dict(deposit_variant=1), dict(deposit_variant=2), dict(deposit_variant=3, fft_z_order=1)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
 def test_variants_are_bit_identical(lib, variant):
     cfg = dict(synth.WORKLOADS["c1_pm32"], n_steps=12)
     ref = run_alone(lib, cfg, 6)
     assert_same(run_alone(lib, cfg, 6, variant), ref, f"variant {variant}")
+
+
+def test_variant_validation(lib):
+    with lib.Sim(**synth.WORKLOADS["c1_pm32"]) as s:
+        before = s.variant
+        for bad in (dict(move_variant=2), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=7)):
+            with pytest.raises(lib.CubeError):
+                s.set_variant(**bad)
+        assert s.variant == before
 
 
 def test_batch_runs_to_the_end(lib):

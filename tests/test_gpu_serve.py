@@ -75,7 +75,7 @@ def test_jobs_in_the_mix_equal_alone(lib):
 
 
 def test_admission_keeps_to_the_budget(lib):
-    cfgs = {i: job(48, 200 + i, n_steps=4) for i in range(4)}
+    cfgs = {i: job(48, 200 + i, n_steps=30) for i in range(4)}
     fp = lib.footprint(**cfgs[0])
     results, seen = {}, []
     with lib.Server(fp + fp // 2, max_active=4, slice_steps=1) as srv:
@@ -98,7 +98,7 @@ def test_failed_job_is_reported_and_others_finish(lib):
         bad = job(32, 300)
         bad["nm_side"], bad["nc_side"] = 40, 10  # not an FFT size: cube_create refuses it at admission
         srv.submit(bad, 1)
-        srv.submit(job(32, 301, n_steps=3), 2)
+        srv.submit(job(32, 301, n_steps=30), 2)
         done, t0 = {}, time.time()
         while len(done) < 2 and time.time() - t0 < 30:
             for i in srv.poll():
