@@ -195,6 +195,12 @@ typedef struct {
   int32_t deposit_variant; /* bit 0: particles of a layer visited with a stride of 1/64 of the layer
                               (lanes of a wavefront in different cells); bit 1: 512-thread
                               workgroups instead of 256; default 3 */
+  int32_t fft_z_layout;    /* 0 (default): z pass in place on the mesh; 1: the forward y pass writes
+                              a z-contiguous copy, the z pass works there and the inverse y pass
+                              writes back (one more mesh-sized device buffer, allocated when chosen
+                              and freed when 0 is set again; not counted by cube_footprint) */
+  int32_t fft_z_width;     /* column width of the z pass on the z-contiguous copy: a supported
+                              width dividing fft_col_width (default: fft_col_width) */
 } cube_variant;
 /* Time the variants on the current state (deposits, solves, then moves whose result is
  * discarded) and keep the fastest of each stage. The particle state is unchanged; the mesh

@@ -8,8 +8,10 @@ fallback of any kind when it is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_int64,
                     c_size_t, c_uint64, c_void_p)
 
@@ -51,7 +53,7 @@ class CubeParams(Structure):
 
 class CubeVariant(Structure):
     _fields_ = [("move_variant", c_int32), ("fft_col_width", c_int32), ("fft_z_order", c_int32),
-                ("deposit_variant", c_int32)]
+                ("deposit_variant", c_int32), ("fft_z_layout", c_int32), ("fft_z_width", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -68,6 +70,19 @@ class CubeStateView(Structure):
 
 
 _lib = None
+
+# Handles still open at interpreter exit are closed before PyTorch (whose allocator frees their
+# device memory) is torn down.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -178,14 +193,16 @@ def _torch_env(torch_memory: bool):
                 dev = torch.cuda.current_device()
                 tstream = torch.cuda.current_stream()
 
+                t_alloc, t_delete = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
+
                 def _alloc(nbytes, _user):
                     try:
-                        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, tstream)
+                        return t_alloc(int(nbytes), dev, tstream)
                     except Exception:  # out of memory: the library reports CUBE_E_NOMEM
                         return None
 
                 def _free(ptr, _user):
-                    torch.cuda.caching_allocator_delete(ptr)
+                    t_delete(ptr)
 
                 a = CubeAllocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
                 keep.append(a)
@@ -218,6 +235,7 @@ class Sim:
         rc = self._lib.cube_create(byref(self.params), stream, alloc_p, byref(self._h))
         if rc != CUBE_OK:
             raise CubeError(rc, "cube_create: " + self._lib.cube_last_error(None).decode())
+        _live.add(self)
 
     def _set_shape(self, p: CubeParams):
         self.np_side, self.nm, self.nc = p.np_side, p.nm_side, p.nc_side
@@ -383,6 +401,8 @@ class Sim:
         unknown = set(changes) - set(cur)
         if unknown:
             raise TypeError(f"unknown variant fields {sorted(unknown)}")
+        if "fft_col_width" in changes and "fft_z_width" not in changes:
+            cur["fft_z_width"] = changes["fft_col_width"]
         cur.update(changes)
         self._check(self._lib.cube_set_variant(self._h, byref(CubeVariant(**cur))))
 
@@ -401,6 +421,7 @@ class Batch:
         rc = self._lib.cube_batch_create(arr, n, stream, alloc_p, byref(self._h))
         if rc != CUBE_OK:
             raise CubeError(rc, "cube_batch_create: " + self._lib.cube_batch_last_error(None).decode())
+        _live.add(self)
         self.boxes = [Sim(**c, _handle=c_void_p(self._lib.cube_batch_box(self._h, i))) for i, c in enumerate(configs)]
 
     def _check(self, rc: int) -> int:
@@ -463,6 +484,7 @@ class Server:
         rc = self._lib.cube_server_create(int(mem_budget_bytes), max_active, slice_steps, alloc_p, byref(self._h))
         if rc != CUBE_OK:
             raise CubeError(rc, "cube_server_create")
+        _live.add(self)
         self._cfg = {}
         self._buf = np.empty(1024, np.int64)
 

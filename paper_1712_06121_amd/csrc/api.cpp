@@ -78,9 +78,15 @@ void build_tables(Sim& s) {
   s.tbucket = static_cast<int16_t*>(s.dmalloc(sizeof(int16_t) * s.nbucket));
   CUBE_HIP(hipMemcpy(s.tbucket, lo.data(), sizeof(int16_t) * s.nbucket, hipMemcpyHostToDevice));
   s.tdec = static_cast<float*>(s.dmalloc(sizeof(float) * m));
-  s.tedge = static_cast<float*>(s.dmalloc(sizeof(float) * (m - 1)));
+  // device edge table with sentinels: ext[0] = -inf, ext[i] = E[i - 1], ext[M] = +inf, so code nu
+  // is the one with ext[nu + h] <= u < ext[nu + h + 1] for every u, end codes included
+  std::vector<float> ext(m + 1);
+  ext[0] = -INFINITY;
+  for (int i = 1; i < m; ++i) ext[i] = s.h_tedge[i - 1];
+  ext[m] = INFINITY;
+  s.tedge = static_cast<float*>(s.dmalloc(sizeof(float) * (m + 1)));
   CUBE_HIP(hipMemcpy(s.tdec, s.h_tdec.data(), sizeof(float) * m, hipMemcpyHostToDevice));
-  CUBE_HIP(hipMemcpy(s.tedge, s.h_tedge.data(), sizeof(float) * (m - 1), hipMemcpyHostToDevice));
+  CUBE_HIP(hipMemcpy(s.tedge, ext.data(), sizeof(float) * (m + 1), hipMemcpyHostToDevice));
 }
 
 void build_schedule(Sim& s) {

@@ -86,6 +86,18 @@ void build_graph(cube_batch& b, int par) {
   CUBE_HIP(hipGraphInstantiate(&b.exec[par], b.graph[par], nullptr, nullptr, 0));
 }
 
+// z layout of the solve: 1 allocates the scratch copy (one mesh-sized buffer) if needed, 0 keeps
+// any allocated scratch, -1 selects 0 and frees the scratch
+void set_z_layout(Sim& s, int layout) {
+  FFTPlan& pl = s.mesh_plan;
+  if (layout == 1 && !pl.zscratch) pl.zscratch = static_cast<float2*>(s.dmalloc(pl.field_floats() * sizeof(float)));
+  if (layout < 0 && pl.zscratch) {
+    s.dfree(pl.zscratch);
+    pl.zscratch = nullptr;
+  }
+  pl.zlayout = layout > 0 ? 1 : 0;
+}
+
 float elapsed_ms(hipEvent_t a, hipEvent_t z) {
   CUBE_HIP(hipEventSynchronize(z));
   float ms = 0.f;
@@ -124,24 +136,48 @@ void autotune_sim(Sim& s) {
     }
   }
   s.deposit_variant = best_d;
-  // FFT column width and z-pass workgroup order
-  int best_bx = s.mesh_plan.colbx, best_z = s.mesh_plan.zorder;
+  // FFT column width, z-pass workgroup order and z layout (the scratch layout only if its buffer
+  // can be allocated)
+  int best_bx = s.mesh_plan.colbx, best_z = s.mesh_plan.zorder, best_l = s.mesh_plan.zlayout;
   best = 1e30f;
-  for (int bx : fft_col_widths(s.nm)) {
-    for (int z = 0; z <= 1; ++z) {
-      s.mesh_plan.colbx = bx;
-      s.mesh_plan.zorder = z;
-      launch_deposit(s, s.stream);
-      const float t = timed([&] { fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr); });
-      if (t < best) {
-        best = t;
-        best_bx = bx;
-        best_z = z;
+  const bool had_scratch = s.mesh_plan.zscratch != nullptr;
+  try {
+    set_z_layout(s, 1);
+  } catch (const Error& e) {
+    if (e.code != CUBE_E_NOMEM) throw;
+  }
+  int best_zbx = s.mesh_plan.zbx;
+  const int max_layout = s.mesh_plan.zscratch ? 1 : 0;
+  const std::vector<int> widths = fft_col_widths(s.nm);
+  for (int l = 0; l <= max_layout; ++l) {
+    for (int bx : widths) {
+      // layout 0: z passes of the same width in either workgroup order; layout 1: z passes of any
+      // width dividing the layout's
+      for (int zb : widths) {
+        if (l == 0 ? zb != bx : bx % zb != 0) continue;
+        for (int z = 0; z <= (l == 0 ? 1 : 0); ++z) {
+          s.mesh_plan.colbx = bx;
+          s.mesh_plan.zbx = zb;
+          s.mesh_plan.zorder = z;
+          s.mesh_plan.zlayout = l;
+          launch_deposit(s, s.stream);
+          const float t = timed([&] { fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr); });
+          if (t < best) {
+            best = t;
+            best_bx = bx;
+            best_zbx = zb;
+            best_z = z;
+            best_l = l;
+          }
+        }
       }
     }
   }
   s.mesh_plan.colbx = best_bx;
+  s.mesh_plan.zbx = best_zbx;
   s.mesh_plan.zorder = best_z;
+  if (best_l == 0 && !had_scratch) CUBE_HIP(hipStreamSynchronize(s.stream));
+  set_z_layout(s, best_l == 0 && !had_scratch ? -1 : best_l);
   launch_deposit(s, s.stream);
   fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
   // move passes: per-corner gradient vs precomputed gradient tile, with this step's factors
@@ -195,6 +231,8 @@ int cube_get_variant(const cube_sim* sim, cube_variant* out) {
   out->fft_col_width = s.mesh_plan.colbx;
   out->fft_z_order = s.mesh_plan.zorder;
   out->deposit_variant = s.deposit_variant;
+  out->fft_z_layout = s.mesh_plan.zlayout;
+  out->fft_z_width = s.mesh_plan.zbx;
   return CUBE_OK;
 }
 
@@ -208,13 +246,24 @@ int cube_set_variant(cube_sim* sim, const cube_variant* v) {
     err = "unsupported FFT column width for this mesh size";
   else if (v->fft_z_order < 0 || v->fft_z_order > 1) err = "fft_z_order must be 0 or 1";
   else if (v->deposit_variant < 0 || v->deposit_variant > 3) err = "deposit_variant must be in 0..3";
+  else if (v->fft_z_layout < 0 || v->fft_z_layout > 1) err = "fft_z_layout must be 0 or 1";
+  else if (std::find(ok.begin(), ok.end(), v->fft_z_width) == ok.end() || v->fft_col_width % v->fft_z_width != 0)
+    err = "fft_z_width must be a supported width dividing fft_col_width";
   if (!err.empty()) {
     s.last_error = err;
     return CUBE_E_INVALID;
   }
+  try {
+    if (v->fft_z_layout != s.mesh_plan.zlayout) CUBE_HIP(hipStreamSynchronize(s.stream));
+    cube::set_z_layout(s, v->fft_z_layout ? 1 : -1);
+  } catch (const Error& e) {
+    s.last_error = e.msg;
+    return e.code;
+  }
   s.move_variant = v->move_variant;
   s.mesh_plan.colbx = v->fft_col_width;
   s.mesh_plan.zorder = v->fft_z_order;
+  s.mesh_plan.zbx = v->fft_z_width;
   s.deposit_variant = v->deposit_variant;
   return CUBE_OK;
 }

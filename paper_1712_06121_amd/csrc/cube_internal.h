@@ -53,6 +53,9 @@ struct FFTPlan {
   int bx = 0;        // row padding (complex values): the widest column block of the y/z passes
   int colbx = 0;     // column block width used by the y/z passes (tunable)
   int zorder = 0;    // workgroup order of the z passes: 0 dispatch order, 1 XCD-contiguous (tunable)
+  int zlayout = 0;   // Poisson solve: 1 = z pass on a z-contiguous scratch copy (tunable)
+  int zbx = 0;       // column block width of the z pass on the scratch copy (divides colbx; tunable)
+  float2* zscratch = nullptr;  // field_floats() floats when allocated (owned by the simulation)
   int pitch_c = 0;   // complex values per row, = n/2 + bx
   float2* tw = nullptr;    // exp(-2 pi i t / n), t = 0..n-1 (device)
   float* k2 = nullptr;     // (2 pi f(t) / n)^2 with f the signed frequency of index t (device)
@@ -101,7 +104,7 @@ struct Sim {
 
   // codec tables (device)
   float* tdec = nullptr;   // M entries
-  float* tedge = nullptr;  // M - 1 entries
+  float* tedge = nullptr;  // M + 1 entries: -inf, the M - 1 edges of Eq. (nu), +inf
   int16_t* tbucket = nullptr;  // first guess of the velocity code per bucket of u / (1 + |u|)
   int nbucket = 0;
   std::vector<float> h_tdec, h_tedge;

@@ -293,16 +293,40 @@ struct ColArgs {
 
 __device__ __forceinline__ int signed_freq(int t, int n) { return t <= n / 2 ? t : t - n; }
 
+// Where complex value c of column block cb, transform index t and other index o lives: at
+// cb * cb_s + o * o_s + t * t_s + c (complex units). The mesh layout has cb_s = BX; the z-contiguous
+// scratch layout [cb][y][z][BX] lets the z transforms read and write contiguous blocks.
+struct ColGeom {
+  int64_t cb_s, t_s, o_s;
+  int cb_r;  // column blocks per layout block: block cb starts at (cb / cb_r) cb_s + (cb % cb_r) BX
+};
+
 template <int N, int MODE, int BX>
 __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2* __restrict__ src, float2* __restrict__ dst,
-                                                                 int64_t tstride, int64_t ostride,
+                                                                 ColGeom gs, ColGeom gt,
                                                                  const float2* __restrict__ tw, ColArgs a) {
   constexpr int BLOCK = ColCfg<N, BX>::BLOCK;
   __shared__ float2 lds[N * BX];
   const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
   const unsigned lb = a.order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
-  const int cb = lb % gridDim.x, o = lb / gridDim.x;
-  const int64_t base = (int64_t)o * ostride + (int64_t)cb * BX;
+  int cb, o;
+  const unsigned paired = (gridDim.x - 1) * gridDim.y;
+  if (a.order == 2 && lb < paired) {
+    // groups of 2 x 2 (column block, other index): four consecutive blocks of one XCD cover whole
+    // 128-byte lines both in the mesh (neighbouring column blocks) and in the scratch layout
+    // (neighbouring other indices); the last column block (Nyquist column) comes after
+    const unsigned g = lb >> 2, r = lb & 3, hc = (gridDim.x - 1) / 2;
+    cb = 2 * (g % hc) + (r & 1);
+    o = 2 * (g / hc) + (r >> 1);
+  } else if (a.order == 2) {
+    cb = gridDim.x - 1;
+    o = lb - paired;
+  } else {
+    cb = lb % gridDim.x;
+    o = lb / gridDim.x;
+  }
+  const int64_t base = (int64_t)o * gs.o_s + (int64_t)(cb / gs.cb_r) * gs.cb_s + (int64_t)(cb % gs.cb_r) * BX;
+  const int64_t tstride = gs.t_s;
   constexpr int Q = BX / 2;
   // every load of the block in flight at once (registers), then into LDS
   constexpr int LPT = N * Q / BLOCK;
@@ -386,10 +410,11 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
   }
   if constexpr (MODE == COL_INV || MODE == COL_GREEN || MODE == COL_PSI)
     fft_lds<N, 1, BX, 1, BX, BLOCK, 1, 1>(lds, tw);
+  const int64_t obase = (int64_t)o * gt.o_s + (int64_t)(cb / gt.cb_r) * gt.cb_s + (int64_t)(cb % gt.cb_r) * BX;
   for (int i = threadIdx.x; i < N * Q; i += BLOCK) {
     const int t = i / Q, c = i % Q;
     const float2 u = lds[t * BX + 2 * c], w = lds[t * BX + 2 * c + 1];
-    *reinterpret_cast<float4*>(dst + base + (int64_t)t * tstride + 2 * c) = make_float4(u.x, u.y, w.x, w.y);
+    *reinterpret_cast<float4*>(dst + obase + (int64_t)t * gt.t_s + 2 * c) = make_float4(u.x, u.y, w.x, w.y);
   }
 }
 
@@ -405,37 +430,62 @@ void run_x(const FFTPlan& pl, float* data, bool forward, hipStream_t st) {
   CUBE_HIP(hipGetLastError());
 }
 
-template <int N, int MODE, int BX>
-void run_col_bx(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
-  const int ncb = (N / 2) / BX + 1;  // the last block holds the Nyquist column and padding
+enum Layout { MESH = 0, ZSCRATCH = 1 };
+
+// strides of the y (axis 1) or z (axis 2) transform in a layout, for column blocks of BX; the
+// scratch layout [b][y][z][LB] groups LB = pl.colbx columns (LB a multiple of BX)
+template <int N, int BX>
+ColGeom col_geom(const FFTPlan& pl, int layout, int axis) {
   const int64_t pc = pl.pitch_c;
-  const int64_t tstride = axis == 1 ? pc : (int64_t)N * pc;
-  const int64_t ostride = axis == 1 ? (int64_t)N * pc : pc;
+  if (layout == MESH) {
+    if (axis == 1) return ColGeom{BX, pc, (int64_t)N * pc, 1};  // t = y, o = z
+    return ColGeom{BX, (int64_t)N * pc, pc, 1};                 // t = z, o = y
+  }
+  const int64_t lb = pl.colbx, blk = (int64_t)N * N * lb;
+  const int r = (int)(lb / BX);
+  if (axis == 1) return ColGeom{blk, (int64_t)N * lb, lb, r};   // t = y, o = z
+  return ColGeom{blk, lb, (int64_t)N * lb, r};                  // t = z, o = y
+}
+
+template <int N, int MODE, int BX>
+void run_col_bx(const FFTPlan& pl, const float* src, int ls, float* dst, int ld, int axis, const ColArgs& a,
+                hipStream_t st) {
+  const int ncb = (N / 2) / BX + 1;  // the last block holds the Nyquist column and padding
   const dim3 grid(ncb, N);
-  k_fft_col<N, MODE, BX><<<grid, ColCfg<N, BX>::BLOCK, 0, st>>>(reinterpret_cast<const float2*>(src),
-                                                                reinterpret_cast<float2*>(dst), tstride, ostride,
-                                                                pl.tw, a);
+  k_fft_col<N, MODE, BX><<<grid, ColCfg<N, BX>::BLOCK, 0, st>>>(
+      reinterpret_cast<const float2*>(src), reinterpret_cast<float2*>(dst), col_geom<N, BX>(pl, ls, axis),
+      col_geom<N, BX>(pl, ld, axis), pl.tw, a);
   CUBE_HIP(hipGetLastError());
 }
 
+// a y or z pass from layout ls to layout ld (MESH or ZSCRATCH) with column blocks of width bx
 template <int N, int MODE>
-void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a0, hipStream_t st) {
+void run_col(const FFTPlan& pl, const float* src, int ls, float* dst, int ld, int axis, const ColArgs& a0,
+             hipStream_t st, int bx) {
   ColArgs a = a0;
-  // y passes: XCD-contiguous ranges share the 128-byte lines of neighbouring column blocks in one
-  // L2; z passes: tunable
-  a.order = axis == 1 ? 1 : pl.zorder;
+  // passes on the mesh along y and passes on the scratch layout: XCD-contiguous ranges
+  // (neighbouring column blocks share 128-byte lines in one L2); y passes between the layouts: 2 x 2
+  // groups when the paired column blocks are even in number; z passes on the mesh: tunable
+  const int ncb = (N / 2) / bx + 1;
+  if (ls != ld) a.order = ((ncb - 1) % 2 == 0) ? 2 : 1;
+  else a.order = (axis == 1 || ls == ZSCRATCH) ? 1 : pl.zorder;
   if constexpr (N < 1024) {
-    if (pl.colbx == 16) {
-      run_col_bx<N, MODE, 16>(pl, src, dst, axis, a, st);
+    if (bx == 16) {
+      run_col_bx<N, MODE, 16>(pl, src, ls, dst, ld, axis, a, st);
       return;
     }
   } else {
-    if (pl.colbx == 4) {
-      run_col_bx<N, MODE, 4>(pl, src, dst, axis, a, st);
+    if (bx == 4) {
+      run_col_bx<N, MODE, 4>(pl, src, ls, dst, ld, axis, a, st);
       return;
     }
   }
-  run_col_bx<N, MODE, 8>(pl, src, dst, axis, a, st);
+  run_col_bx<N, MODE, 8>(pl, src, ls, dst, ld, axis, a, st);
+}
+
+template <int N, int MODE>
+void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const ColArgs& a, hipStream_t st) {
+  run_col<N, MODE>(pl, src, MESH, dst, MESH, axis, a, st, pl.colbx);
 }
 
 template <int N>
@@ -444,11 +494,21 @@ void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st, hipEvent
   if (ev) CUBE_HIP(hipEventRecord(ev[0], st));
   run_x<N>(pl, d, true, st);
   if (ev) CUBE_HIP(hipEventRecord(ev[1], st));
-  run_col<N, COL_FWD>(pl, d, d, 1, a, st);
-  if (ev) CUBE_HIP(hipEventRecord(ev[2], st));
-  run_col<N, COL_GREEN>(pl, d, d, 2, a, st);
-  if (ev) CUBE_HIP(hipEventRecord(ev[3], st));
-  run_col<N, COL_INV>(pl, d, d, 1, a, st);
+  if (pl.zlayout && pl.zscratch) {
+    // y pass into the z-contiguous scratch, z pass + Green's function there, y pass back
+    float* zs = reinterpret_cast<float*>(pl.zscratch);
+    run_col<N, COL_FWD>(pl, d, MESH, zs, ZSCRATCH, 1, a, st, pl.colbx);
+    if (ev) CUBE_HIP(hipEventRecord(ev[2], st));
+    run_col<N, COL_GREEN>(pl, zs, ZSCRATCH, zs, ZSCRATCH, 2, a, st, pl.zbx);
+    if (ev) CUBE_HIP(hipEventRecord(ev[3], st));
+    run_col<N, COL_INV>(pl, zs, ZSCRATCH, d, MESH, 1, a, st, pl.colbx);
+  } else {
+    run_col<N, COL_FWD>(pl, d, d, 1, a, st);
+    if (ev) CUBE_HIP(hipEventRecord(ev[2], st));
+    run_col<N, COL_GREEN>(pl, d, d, 2, a, st);
+    if (ev) CUBE_HIP(hipEventRecord(ev[3], st));
+    run_col<N, COL_INV>(pl, d, d, 1, a, st);
+  }
   if (ev) CUBE_HIP(hipEventRecord(ev[4], st));
   run_x<N>(pl, d, false, st);
   if (ev) CUBE_HIP(hipEventRecord(ev[5], st));
@@ -510,6 +570,7 @@ void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
   pl.n = n;
   pl.bx = col_bx_pitch(n);
   pl.colbx = col_bx_default(n);
+  pl.zbx = pl.colbx;
   pl.zorder = 0;
   pl.pitch_c = n / 2 + pl.bx;
   std::vector<float2> tw(n);

@@ -225,7 +225,7 @@ struct MoveArgs {
   int64_t nc3;
   float kf, df;
   const float* tdec;
-  const float* tedge;
+  const float* tedge;  // edge table with -inf / +inf sentinels (M + 1 entries)
   const int16_t* tbucket;
   int nbucket;
   int vhalf;
@@ -310,6 +310,45 @@ __device__ __forceinline__ float grad_at(const float* ph, const float* gd, int d
   }
 }
 
+// New coarse cell along one dimension: k in {-1, 0, 1}, the code of the position inside it, and
+// whether the value is usable; a non-finite value, a move beyond one coarse cell or a speed beyond
+// the range of the moment accumulators raises its error flag. In range (the usual case) only the
+// first branch runs; NaN fails its comparisons.
+template <int SH>
+__device__ __forceinline__ bool new_cell(float ln, float vd, uint32_t* flags, int& k, int& cq) {
+  bool ok = true;
+  float lw;
+  if (ln >= -4.0f && ln < 8.0f && fabsf(vd) < 32768.0f) {
+    k = ln < 0.0f ? -1 : (ln >= 4.0f ? 1 : 0);
+    lw = k == 0 ? ln : (k < 0 ? ln + 4.0f : ln - 4.0f);
+  } else {
+    k = 0;
+    lw = ln;
+    if (!(ln == ln) || fabsf(ln) == INFINITY || !(vd == vd) || fabsf(vd) == INFINITY) {
+      set_flag(flags, FLAG_NONFINITE);
+      ok = false;
+      lw = 0.0f;
+    } else if (ln < -4.0f || ln >= 8.0f) {
+      set_flag(flags, FLAG_CFL);
+      ok = false;
+      lw = 0.0f;
+    } else if (ln < 0.0f) {
+      k = -1;
+      lw = ln + 4.0f;
+    } else if (ln >= 4.0f) {
+      k = 1;
+      lw = ln - 4.0f;
+    }
+    if (fabsf(vd) >= 32768.0f) {
+      set_flag(flags, FLAG_OVERFLOW);
+      ok = false;
+    }
+  }
+  int q = (int)floorf(lw * (float)(1 << (SH - 1)));
+  cq = q < 0 ? 0 : (q > (1 << (SH + 1)) - 1 ? (1 << (SH + 1)) - 1 : q);
+  return ok;
+}
+
 template <int NCHI, int NNU, int MODE, bool PRE>
 __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* ph, const float* gd, int s, int64_t p,
                                                uint32_t li, const TileGeom& g) {
@@ -356,8 +395,8 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
         const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
         i0[d] = pl >> SH;
         const int f = pl & ((1 << SH) - 1);
-        w0[d] = (float)((1 << SH) - f) * wunit;
         w1[d] = (float)f * wunit;
+        w0[d] = 1.0f - w1[d];  // exact: both are multiples of 2^-SH in [0, 1]
       }
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -383,30 +422,8 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
   m.ok = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const float ln = l[d];
-    int k = 0;
-    float lw = ln;
-    if (!(ln == ln) || fabsf(ln) == INFINITY || !(v[d] == v[d]) || fabsf(v[d]) == INFINITY) {
-      set_flag(a.flags, FLAG_NONFINITE);
-      m.ok = false;
-      lw = 0.0f;
-    } else if (ln < -4.0f || ln >= 8.0f) {
-      set_flag(a.flags, FLAG_CFL);
-      m.ok = false;
-      lw = 0.0f;
-    } else if (ln < 0.0f) {
-      k = -1;
-      lw = ln + 4.0f;
-    } else if (ln >= 4.0f) {
-      k = 1;
-      lw = ln - 4.0f;
-    }
-    if (fabsf(v[d]) >= 32768.0f) {
-      set_flag(a.flags, FLAG_OVERFLOW);
-      m.ok = false;
-    }
-    int cq = (int)floorf(lw * (float)(1 << (SH - 1)));
-    cq = cq < 0 ? 0 : (cq > (1 << (SH + 1)) - 1 ? (1 << (SH + 1)) - 1 : cq);
+    int k, cq;
+    if (!new_cell<SH>(l[d], v[d], a.flags, k, cq)) m.ok = false;
     m.k[d] = k;
     m.chi[d] = cq;
     m.v[d] = m.ok ? v[d] : 0.0f;
@@ -604,16 +621,21 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
   }
 }
 
-// Eq. (nu) by the edge table: the code nu with E[nu + h - 1] <= u < E[nu + h] (h = (M-1)/2), i.e.
-// -h + #{edges <= u}. A bucket table over t = u / (1 + |u|) gives a starting code; the two loops
-// then settle on the exact code whatever the start, so the result equals a full search.
-__device__ __forceinline__ int encode_nu(float u, const float* edges, const int16_t* bucket, int nbucket, int vhalf) {
-  const float t = u / (1.0f + fabsf(u));
+// Eq. (nu) by the edge table: the code nu with ext[nu + h] <= u < ext[nu + h + 1] (h = (M-1)/2;
+// ext is the edge table with -inf and +inf at its ends), i.e. -h + #{edges <= u}. A bucket table
+// over t = u / (1 + |u|) gives the code at the lower end of the bucket, within two codes of the
+// answer (each bucket holds at most one edge, and an approximate t can miss its bucket by one);
+// two exact steps reach it, and the loops behind them (normally not entered) make the result exact
+// whatever the start.
+__device__ __forceinline__ int encode_nu(float u, const float* ext, const int16_t* bucket, int nbucket, int vhalf) {
+  const float t = u * __builtin_amdgcn_rcpf(1.0f + fabsf(u));
   int b = (int)((t + 1.0f) * (0.5f * (float)nbucket));
   b = b < 0 ? 0 : (b > nbucket - 1 ? nbucket - 1 : b);
   int nu = bucket[b];
-  while (nu < vhalf && u >= edges[nu + vhalf]) ++nu;
-  while (nu > -vhalf && u < edges[nu + vhalf - 1]) --nu;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) nu += (int)(u >= ext[nu + vhalf + 1]) - (int)(u < ext[nu + vhalf]);
+  while (u >= ext[nu + vhalf + 1]) ++nu;
+  while (u < ext[nu + vhalf]) --nu;
   return nu;
 }
 
@@ -628,12 +650,12 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   __shared__ uint32_t pre[TC + 1];
   __shared__ uint64_t start[TC];
   __shared__ uint32_t wsum[NTH / 64];
-  __shared__ float edges_lds[NNU == 1 ? 254 : 1];
+  __shared__ float edges_lds[NNU == 1 ? 256 : 1];
   __shared__ int16_t bucket_lds[NNU == 1 ? 1024 : 1];
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
-  const int nedge = 2 * a.vhalf;
+  const int nedge = 2 * a.vhalf + 2;
   if constexpr (NNU == 1) {
     for (int i = threadIdx.x; i < nedge; i += NTH) edges_lds[i] = a.tedge[i];
     for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = a.tbucket[i];
@@ -729,31 +751,69 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 template <int NCHI, int NNU, bool SCATTER>
-__global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
+// two 1024-thread workgroups per CU: at most 64 VGPRs
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_move_dense(MoveArgs a) {
   resolve_factors(a);
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
   constexpr int NTH = 1024;
   constexpr int SH = 8 * NCHI - 1;
-  __shared__ float ph[PH * PH * PH];
-  __shared__ float gd[3 * DG * DG * DG];
+  // one region holds the potential tile, then the gradient tile computed from it: with the
+  // moments added to the global accumulators directly, two workgroups fit a CU
+  constexpr int NG = 3 * DG * DG * DG;
+  static_assert(PH * PH * PH <= NG, "the potential tile must fit the gradient region");
+  __shared__ float tile[NG];
+  float* const ph = tile;
+  float* const gd = tile;
   __shared__ uint32_t grp[TC * 27];              // count pass: per (cell, displacement) counts; scatter: ranks
-  __shared__ unsigned long long mom[SCATTER ? 1 : RC * 4];
   __shared__ uint32_t pre[TC + 1];
   __shared__ uint64_t start[TC];
   __shared__ uint32_t wsum[NTH / 64];
   __shared__ float tdec_lds[NNU == 1 ? 255 : 1];
-  __shared__ float edges_lds[(SCATTER && NNU == 1) ? 254 : 1];
+  __shared__ float edges_lds[(SCATTER && NNU == 1) ? 256 : 1];
   __shared__ int16_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
-  load_potential<0, true, NTH>(a, ph, gd, g);
+  load_potential<0, false, NTH>(a, ph, nullptr, g);
+  __syncthreads();
+  {
+    // gradient of every corner cell -1 .. F of the tile, over the potential: the z component lies
+    // beyond the potential tile and is stored at once; x and y go through registers
+    constexpr int G3 = DG * DG * DG;
+    static_assert(2 * G3 >= PH * PH * PH, "the z gradient must not overlap the potential tile");
+    constexpr int K = (G3 + NTH - 1) / NTH;
+    auto grad_of = [&](int d, int i) {
+      const int z = i / (DG * DG), y = (i / DG) % DG, x = i % DG;
+      return grad_at<false>(ph, nullptr, d, x - 1, y - 1, z - 1);
+    };
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (G3 % NTH == 0 || i < G3) gd[2 * G3 + i] = grad_of(2, i);
+    }
+    float gx[K], gy[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (G3 % NTH == 0 || i < G3) {
+        gx[k] = grad_of(0, i);
+        gy[k] = grad_of(1, i);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (G3 % NTH == 0 || i < G3) {
+        gd[i] = gx[k];
+        gd[G3 + i] = gy[k];
+      }
+    }
+  }
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
-  if constexpr (!SCATTER)
-    for (int i = threadIdx.x; i < RC * 4; i += NTH) mom[i] = 0ull;
   if constexpr (NNU == 1) {
     for (int i = threadIdx.x; i < 255; i += NTH) tdec_lds[i] = a.tdec[i];
     if constexpr (SCATTER) {
-      for (int i = threadIdx.x; i < 254; i += NTH) edges_lds[i] = a.tedge[i];
+      for (int i = threadIdx.x; i < 256; i += NTH) edges_lds[i] = a.tedge[i];
       for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = a.tbucket[i];
     }
   }
@@ -778,7 +838,6 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
     const CT* chx = static_cast<const CT*>(a.chi) + base;
     const NT* nux = static_cast<const NT*>(a.nu) + base;
     const float vcx = a.vc[c], vcy = a.vc[a.nc3 + c], vcz = a.vc[2 * a.nc3 + c], vsc = a.vs[c];
-    const int r_stay = (o0 + 1) + RG * ((o1 + 1) + RG * (o2 + 1));
     for (uint32_t j0 = 0; j0 < n; j0 += 64) {
       const uint32_t j = j0 + lane;
       const bool active = j < n;
@@ -803,8 +862,8 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
           const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
           i0[d] = pl >> SH;
           const int f = pl & ((1 << SH) - 1);
-          w0[d] = (float)((1 << SH) - f) * unit;
           w1[d] = (float)f * unit;
+          w0[d] = 1.0f - w1[d];  // exact: both are multiples of 2^-SH in [0, 1]
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -830,34 +889,8 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
       int k[3], cq[3];
       bool ok = true;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const float ln = l[d];
-        int kk = 0;
-        float lw = ln;
-        if (!(ln == ln) || fabsf(ln) == INFINITY || !(v[d] == v[d]) || fabsf(v[d]) == INFINITY) {
-          set_flag(a.flags, FLAG_NONFINITE);
-          ok = false;
-          lw = 0.0f;
-        } else if (ln < -4.0f || ln >= 8.0f) {
-          set_flag(a.flags, FLAG_CFL);
-          ok = false;
-          lw = 0.0f;
-        } else if (ln < 0.0f) {
-          kk = -1;
-          lw = ln + 4.0f;
-        } else if (ln >= 4.0f) {
-          kk = 1;
-          lw = ln - 4.0f;
-        }
-        if (fabsf(v[d]) >= 32768.0f) {
-          set_flag(a.flags, FLAG_OVERFLOW);
-          ok = false;
-        }
-        int q = (int)floorf(lw * (float)(1 << (SH - 1)));
-        q = q < 0 ? 0 : (q > (1 << (SH + 1)) - 1 ? (1 << (SH + 1)) - 1 : q);
-        k[d] = kk;
-        cq[d] = q;
-      }
+      for (int d = 0; d < 3; ++d)
+        if (!new_cell<SH>(l[d], v[d], a.flags, k[d], cq[d])) ok = false;
       if (!ok) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) v[d] = 0.0f;
@@ -874,13 +907,16 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
         if (lane == 0 && smask) {
           atomicAdd(&grp[s * 27 + 13], (uint32_t)__popcll(smask));
 #pragma unroll
-          for (int d = 0; d < 4; ++d) atomicAdd(&mom[r_stay * 4 + d], tot[d]);
+          for (int d = 0; d < 4; ++d) atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + c]), tot[d]);
         }
         if (active && !stay) {
-          const int r = r_stay + k[0] + RG * (k[1] + RG * k[2]);
           atomicAdd(&grp[s * 27 + dcode], 1u);
+          const int nx = wrapi(g.cx0 + o0 + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
+          const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
+          const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
 #pragma unroll
-          for (int d = 0; d < 4; ++d) atomicAdd(&mom[r * 4 + d], (unsigned long long)q[d]);
+          for (int d = 0; d < 4; ++d)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
         }
       } else {
         unsigned long long peers = __ballot(active);
@@ -927,15 +963,6 @@ __global__ __launch_bounds__(1024) void k_move_dense(MoveArgs a) {
       const int s = i / 27, d = i % 27;
       const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
       a.mig[d * a.nc3 + c] = grp[i];
-    }
-    for (int i = threadIdx.x; i < RC * 4; i += NTH) {
-      const unsigned long long v = mom[i];
-      if (v == 0ull) continue;
-      const int r = i / 4, q = i % 4;
-      const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
-      const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
-      const int64_t c = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[q * a.nc3 + c]), v);
     }
   }
 }
