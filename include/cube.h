@@ -184,10 +184,12 @@ int cube_get_timings(const cube_sim* sim, double* ms9);
  * Some stages have equivalent kernel variants that give bit-identical results: the layout of the
  * work, never the arithmetic, differs. */
 typedef struct {
-  int32_t move_variant;    /* 0 (default): 4-point gradient per CIC corner, 512-thread workgroups;
-                              1: gradient of the whole tile precomputed in LDS, one coarse cell per
-                              wavefront, 1024-thread workgroups; -1: 1 when there are at least half
-                              as many particles as fine cells, else 0 */
+  int32_t move_variant;    /* which move passes use the gradient tile (the 4-point gradient of the
+                              whole tile precomputed in LDS, one row of coarse cells per wavefront,
+                              1024-thread workgroups) instead of the gradient per CIC corner
+                              (512-thread workgroups): 0 (default) neither, 1 both, 2 the scatter
+                              pass, 3 the count pass; -1: both when there are at least half as many
+                              particles as fine cells, else neither */
   int32_t fft_col_width;   /* complex columns per workgroup in the y/z passes: 8 or 16 for
                               nm_side <= 512, 4 or 8 above */
   int32_t fft_z_order;     /* workgroup order of the z passes: 0 dispatch order, 1 contiguous ranges

@@ -180,24 +180,27 @@ void autotune_sim(Sim& s) {
   set_z_layout(s, best_l == 0 && !had_scratch ? -1 : best_l);
   launch_deposit(s, s.stream);
   fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
-  // move passes: per-corner gradient vs precomputed gradient tile, with this step's factors
+  // move passes: per-corner gradient vs precomputed gradient tile, each pass timed on its own
+  // (events around the count and the scatter pass), with this step's factors
   const int j = std::min(s.steps_done, s.p.n_steps - 1);
   const float kf = (float)(-s.kicks[j] / 12.0), df = (float)s.drifts[j];
-  int best_v = 0;
-  best = 1e30f;
+  float tc[2] = {0.f, 0.f}, ts[2] = {0.f, 0.f};
+  hipEvent_t* me = s.ev + 8;  // four events: before count, after count, after link, after scatter
   for (int v = 0; v <= 1; ++v) {
     s.move_variant = v;
-    const float t = timed([&] {
+    for (int r = 0; r <= reps; ++r) {
       const int cur = s.cur;
-      launch_move(s, 0, kf, df, nullptr, 0.0f, s.stream, nullptr);
+      launch_move(s, 0, kf, df, nullptr, 0.0f, s.stream, me);
       s.cur = cur;  // discard the result
-    });
-    if (t < best) {
-      best = t;
-      best_v = v;
+      const float c = elapsed_ms(me[0], me[1]), sc = elapsed_ms(me[2], me[3]);
+      if (r > 0) {
+        tc[v] += c;
+        ts[v] += sc;
+      }
     }
   }
-  s.move_variant = best_v;
+  const bool tcnt = tc[1] < tc[0], tsct = ts[1] < ts[0];
+  s.move_variant = tcnt ? (tsct ? 1 : 3) : (tsct ? 2 : 0);
   // a timed move may have raised a flag that the real step will raise again; clear it here
   CUBE_HIP(hipMemsetAsync(s.flags, 0, sizeof(uint32_t), s.stream));
   CUBE_HIP(hipStreamSynchronize(s.stream));
@@ -241,7 +244,7 @@ int cube_set_variant(cube_sim* sim, const cube_variant* v) {
   cube::Sim& s = sim->s;
   const std::vector<int> ok = cube::fft_col_widths(s.nm);
   std::string err;
-  if (v->move_variant < -1 || v->move_variant > 1) err = "move_variant must be -1, 0 or 1";
+  if (v->move_variant < -1 || v->move_variant > 3) err = "move_variant must be in -1..3";
   else if (std::find(ok.begin(), ok.end(), v->fft_col_width) == ok.end())
     err = "unsupported FFT column width for this mesh size";
   else if (v->fft_z_order < 0 || v->fft_z_order > 1) err = "fft_z_order must be 0 or 1";

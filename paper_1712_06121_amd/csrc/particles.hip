@@ -627,7 +627,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
 // answer (each bucket holds at most one edge, and an approximate t can miss its bucket by one);
 // two exact steps reach it, and the loops behind them (normally not entered) make the result exact
 // whatever the start.
-__device__ __forceinline__ int encode_nu(float u, const float* ext, const int16_t* bucket, int nbucket, int vhalf) {
+template <typename BT>
+__device__ __forceinline__ int encode_nu(float u, const float* ext, const BT* bucket, int nbucket, int vhalf) {
   const float t = u * __builtin_amdgcn_rcpf(1.0f + fabsf(u));
   int b = (int)((t + 1.0f) * (0.5f * (float)nbucket));
   b = b < 0 ? 0 : (b > nbucket - 1 ? nbucket - 1 : b);
@@ -727,12 +728,31 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
 // (the large majority) are summed with one cross-lane reduction; particles of a cell are visited
 // in storage order by a single wave, which makes the running rank per displacement exact.
 // ---------------------------------------------------------------------------------------------
-template <unsigned CTRL>
+template <unsigned CTRL, unsigned ROWS = 0xF>
 __device__ __forceinline__ unsigned long long dpp_add_u64(unsigned long long v) {
   const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, 0xF, 0xF, false);
-  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, 0xF, 0xF, false);
+  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xF, false);
+  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xF, false);
   return v + (((unsigned long long)h2 << 32) | l2);
+}
+
+// inclusive prefix sum over the 64 lanes (every lane active): shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes, then the totals of rows 0 and 2 into rows 1 and 3, then that of rows 0-1 into
+// rows 2 and 3
+__device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long v) {
+  v = dpp_add_u64<0x111>(v);        // row_shr:1
+  v = dpp_add_u64<0x112>(v);        // row_shr:2
+  v = dpp_add_u64<0x114>(v);        // row_shr:4
+  v = dpp_add_u64<0x118>(v);        // row_shr:8
+  v = dpp_add_u64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add_u64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // sum over the 64 lanes (every lane active), returned to all lanes
@@ -771,7 +791,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   __shared__ uint32_t wsum[NTH / 64];
   __shared__ float tdec_lds[NNU == 1 ? 255 : 1];
   __shared__ float edges_lds[(SCATTER && NNU == 1) ? 256 : 1];
-  __shared__ int16_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];
+  __shared__ int8_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];  // 1-byte codes fit int8
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<0, false, NTH>(a, ph, nullptr, g);
   __syncthreads();
@@ -814,14 +834,22 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     for (int i = threadIdx.x; i < 255; i += NTH) tdec_lds[i] = a.tdec[i];
     if constexpr (SCATTER) {
       for (int i = threadIdx.x; i < 256; i += NTH) edges_lds[i] = a.tedge[i];
-      for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = a.tbucket[i];
+      for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = (int8_t)a.tbucket[i];
     }
   }
   const float* tdec = NNU == 1 ? tdec_lds : a.tdec;
   const float* edges = NNU == 1 ? edges_lds : a.tedge;
-  const int16_t* bucket = NNU == 1 ? bucket_lds : a.tbucket;
-  __shared__ uint32_t next_cell;
-  if (threadIdx.x == 0) next_cell = NTH / 64;
+  using BT = std::conditional_t<NNU == 1, int8_t, int16_t>;
+  const BT* bucket;
+  if constexpr (NNU == 1) bucket = bucket_lds;
+  else bucket = a.tbucket;
+  // mean velocity and decode scale of the tile's cells
+  __shared__ float4 cellv[TC];
+  if (threadIdx.x < TC) {
+    const int sx = threadIdx.x;
+    const int64_t c = (g.cx0 + sx % T) + (int64_t)a.nc * ((g.cy0 + (sx / T) % T) + (int64_t)a.nc * (g.cz0 + sx / (T * T)));
+    cellv[sx] = make_float4(a.vc[c], a.vc[a.nc3 + c], a.vc[2 * a.nc3 + c], a.vs[c]);
+  }
   own_cells<0>(a, g, pre, start, wsum);  // ends with a barrier
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -829,32 +857,39 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   const float unit = (float)(1.0 / (double)(1 << SH));
   CT* chi_n = static_cast<CT*>(a.chi_n);
   NT* nu_n = static_cast<NT*>(a.nu_n);
-  // cells are handed out one at a time, so a wave that drew a crowded cell does not hold up the rest
-  for (int s = wave; s < TC;) {
-    const int o0 = s % T, o1 = (s / T) % T, o2 = s / (T * T);
-    const int64_t c = (g.cx0 + o0) + (int64_t)a.nc * ((g.cy0 + o1) + (int64_t)a.nc * (g.cz0 + o2));
-    const uint32_t n = pre[s + 1] - pre[s];
-    const uint64_t base = start[s];
+  // Each wave takes one row of T cells along x (16 rows, 16 waves): their particles are contiguous
+  // in storage, so the wave's chunks of 64 lanes stay full across cell boundaries. A lane's cell in
+  // the row follows from the row's prefix counts.
+  static_assert(T == 4 && TC / T == NTH / 64, "one row of four cells per wave");
+  {
+    const int row = wave;
+    const int s0 = T * row, o1 = row % T, o2 = row / T;
+    const uint32_t p1 = pre[s0 + 1] - pre[s0], p2 = pre[s0 + 2] - pre[s0], p3 = pre[s0 + 3] - pre[s0];
+    const uint32_t nrow = pre[s0 + 4] - pre[s0];
+    const uint64_t base = start[s0];
     const CT* chx = static_cast<const CT*>(a.chi) + base;
     const NT* nux = static_cast<const NT*>(a.nu) + base;
-    const float vcx = a.vc[c], vcy = a.vc[a.nc3 + c], vcz = a.vc[2 * a.nc3 + c], vsc = a.vs[c];
-    for (uint32_t j0 = 0; j0 < n; j0 += 64) {
+    const int64_t crow = (int64_t)a.nc * ((g.cy0 + o1) + (int64_t)a.nc * (g.cz0 + o2));
+    for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
       const uint32_t j = j0 + lane;
-      const bool active = j < n;
+      const bool active = j < nrow;
+      const int ci = (int)(j >= p1) + (int)(j >= p2) + (int)(j >= p3);  // cell of the row
+      const int s = s0 + ci;
       float v[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
       int ch[3] = {0, 0, 0};
       if (active) {
-        const float vcv[3] = {vcx, vcy, vcz};
+        const float4 cv = cellv[s];
+        const float vcv[3] = {cv.x, cv.y, cv.z};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           ch[d] = (int)chx[d * a.cap + j];
           int nuv = (int)nux[d * a.cap + j];
           nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
           l[d] = (float)(2 * ch[d] + 1) * unit;
-          v[d] = vcv[d] + vsc * tdec[nuv + a.vhalf];
+          v[d] = vcv[d] + cv.w * tdec[nuv + a.vhalf];
         }
         // CIC corners relative to the tile, exact dyadic weights, interpolated gradient
-        const int o[3] = {o0, o1, o2};
+        const int o[3] = {ci, o1, o2};
         int i0[3];
         float w0[3], w1[3];
 #pragma unroll
@@ -901,17 +936,36 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         velocity_moments(v, q);  // inactive lanes hold v = 0
         const bool stay = active && dcode == 13;
         const unsigned long long smask = __ballot(stay);
-        unsigned long long tot[4];
+        // stayers: one prefix sum over the chunk, then the difference over each cell's lanes
+        unsigned long long ps[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) tot[d] = wave_sum_u64(stay ? (unsigned long long)q[d] : 0ull);
-        if (lane == 0 && smask) {
-          atomicAdd(&grp[s * 27 + 13], (uint32_t)__popcll(smask));
+        for (int d = 0; d < 4; ++d) ps[d] = wave_scan_u64(stay ? (unsigned long long)q[d] : 0ull);
+        const int cfirst = __builtin_amdgcn_readfirstlane(ci);
+        const uint32_t jend = nrow - j0 < 64u ? nrow - j0 : 64u;  // active lanes
+        const int clast = __builtin_amdgcn_readlane(ci, (int)jend - 1);
+        const uint32_t bnd[5] = {0u, p1, p2, p3, nrow};
+        for (int cc = cfirst; cc <= clast; ++cc) {
+          const int la = (int)(bnd[cc] > j0 ? bnd[cc] - j0 : 0u);
+          const int lb = (int)((bnd[cc + 1] - j0 < jend ? bnd[cc + 1] - j0 : jend)) - 1;
+          if (la > lb) continue;
+          const unsigned long long seg = (lb == 63 ? ~0ull : ((2ull << lb) - 1ull)) & ~((1ull << la) - 1ull);
+          const int nst = __popcll(smask & seg);
+          if (nst == 0) continue;
+          unsigned long long tot[4];
 #pragma unroll
-          for (int d = 0; d < 4; ++d) atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + c]), tot[d]);
+          for (int d = 0; d < 4; ++d)
+            tot[d] = read_lane_u64(ps[d], lb) - (la > 0 ? read_lane_u64(ps[d], la - 1) : 0ull);
+          if (lane == 0) {
+            const int64_t c = (g.cx0 + cc) + crow;
+            atomicAdd(&grp[(s0 + cc) * 27 + 13], (uint32_t)nst);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + c]), tot[d]);
+          }
         }
         if (active && !stay) {
           atomicAdd(&grp[s * 27 + dcode], 1u);
-          const int nx = wrapi(g.cx0 + o0 + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
+          const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
           const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
           const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
 #pragma unroll
@@ -919,10 +973,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
         }
       } else {
+        // lanes with the same (cell of the row, displacement): rank among them in storage order
+        const int key = (ci << 5) | dcode;
         unsigned long long peers = __ballot(active);
 #pragma unroll
-        for (int b = 0; b < 5; ++b) {
-          const bool bit = (dcode >> b) & 1;
+        for (int b = 0; b < 7; ++b) {
+          const bool bit = (key >> b) & 1;
           const unsigned long long bb = __ballot(active && bit);
           peers &= bit ? bb : ~bb;
         }
@@ -935,7 +991,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
         gbase = (uint32_t)__shfl((int)gbase, leader, 64);
         if (active) {
-          const int nx = wrapi(g.cx0 + o0 + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
+          const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
           const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
           const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
           const uint64_t dst = a.off_n[cn] + a.slot[(int64_t)(26 - dcode) * a.nc3 + cn] + gbase + (uint32_t)rin;
@@ -953,9 +1009,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
       }
     }
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(&next_cell, 1u);
-    s = __builtin_amdgcn_readfirstlane((int)t);
   }
   if constexpr (!SCATTER) {
     __syncthreads();
@@ -1368,17 +1421,21 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   }
   const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
   // precomputed gradient tile when particles are at least half as many as fine cells
-  const bool pre = mode == 0 && (s.move_variant < 0 ? 2 * s.n >= (int64_t)s.nm * s.nm * s.nm : s.move_variant == 1);
+  // gradient tile per pass: variant 1 both, 2 scatter only, 3 count only, -1 by density
+  const bool dense = 2 * s.n >= (int64_t)s.nm * s.nm * s.nm;
+  const int mv = s.move_variant;
+  const bool tile_count = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 3));
+  const bool tile_scatter = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 2));
 #define CUBE_COUNT(X, V)                                                                        \
   do {                                                                                          \
-    if (mode == 0 && pre) k_move_dense<X, V, false><<<grid, 1024, 0, st>>>(a);                   \
+    if (tile_count) k_move_dense<X, V, false><<<grid, 1024, 0, st>>>(a);                         \
     else if (mode == 0) k_move_count<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);              \
     else if (mode == 1) k_move_count<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);              \
     else k_move_count<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                             \
   } while (0)
 #define CUBE_SCATTER(X, V)                                                                      \
   do {                                                                                          \
-    if (mode == 0 && pre) k_move_dense<X, V, true><<<grid, 1024, 0, st>>>(a);                    \
+    if (tile_scatter) k_move_dense<X, V, true><<<grid, 1024, 0, st>>>(a);                        \
     else if (mode == 0) k_move_scatter<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);            \
     else if (mode == 1) k_move_scatter<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);            \
     else k_move_scatter<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                           \

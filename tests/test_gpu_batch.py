@@ -73,6 +73,7 @@ def test_batch_autotune_keeps_results(lib):
 
 
 VARIANTS = [dict(move_variant=0, fft_col_width=8), dict(move_variant=1, fft_col_width=8),
+            dict(move_variant=2), dict(move_variant=3), dict(move_variant=-1),
             dict(move_variant=0, fft_col_width=16, fft_z_order=1), dict(move_variant=1, fft_col_width=16),
             dict(deposit_variant=1), dict(deposit_variant=2), dict(deposit_variant=3, fft_z_order=1),
             dict(fft_z_layout=1), dict(fft_z_layout=1, fft_col_width=16),
@@ -89,7 +90,7 @@ def test_variants_are_bit_identical(lib, variant):
 def test_variant_validation(lib):
     with lib.Sim(**synth.WORKLOADS["c1_pm32"]) as s:
         before = s.variant
-        for bad in (dict(move_variant=2), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=7),
+        for bad in (dict(move_variant=4), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=7),
                     dict(fft_z_layout=2), dict(fft_col_width=8, fft_z_width=16)):
             with pytest.raises(lib.CubeError):
                 s.set_variant(**bad)
