@@ -119,21 +119,27 @@ def bench_ensemble(args) -> dict:
     b.autotune()
     b.step(args.warmup)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(args.steps)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
+    # both launch modes, each over the same number of steps (the second continues the run)
+    t_mode = {}
+    for mode, name in ((Batch.STREAMS, "streams"), (Batch.GRAPH, "graph")):
+        b.set_mode(mode)
+        t0 = time.perf_counter()
+        b.step(args.steps)
+        torch.cuda.synchronize()
+        t_mode[name] = time.perf_counter() - t0
+    best_mode = min(t_mode, key=t_mode.get)
+    t_batch = t_mode[best_mode]
     ref0 = b.boxes[0].get_state()
     variants = sorted({(c["np_side"], tuple(box.variant.values())) for c, box in zip(cfgs, b.boxes)})
     dev_bytes = sum(box.device_bytes for box in b.boxes)
     b.close()
-    print(f"[bench] batch: {args.steps} steps in {t_batch:.3f} s, variants {variants}", file=sys.stderr, flush=True)
+    print(f"[bench] batch: {args.steps} steps in {t_mode}, variants {variants}", file=sys.stderr, flush=True)
     t_seq = 0.0
     same0 = None
     for i, c in enumerate(cfgs):
         with Sim(**c) as s:
             s.init_ic()
-            s.step(args.warmup)
+            s.step(args.warmup + args.steps)  # box 0 is compared with the batch at the same step
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.step(args.steps)
@@ -167,6 +173,8 @@ def bench_ensemble(args) -> dict:
                      "frac": step_bytes / k_step / 1e9 / HBM_PEAK_GBS, "traffic": None},
         "sequential": {"value": total * args.steps / t_seq, "seconds": t_seq},
         "speedup_vs_sequential": t_seq / t_batch,
+        "batch_seconds_by_mode": t_mode,
+        "batch_mode": best_mode,
         "box0_bit_identical": same0,
         "cpu_baseline": None,
     }

@@ -143,6 +143,9 @@ typedef struct {
   int32_t steps_done;
 } cube_state_view;
 int cube_get_state(cube_sim* sim, cube_state_view* out);
+/* The particle count of every coarse cell (nc^3 uint32, x-fastest) into host memory: the part of
+ * the state that is small at any size (rho_c of Sec. 2.3.1). */
+int cube_get_counts(cube_sim* sim, uint32_t* cnt);
 int cube_set_state(cube_sim* sim, const cube_state_view* in);
 
 /* ---- stages of one step, for parity checks and profiling -------------------------------- */
@@ -235,6 +238,10 @@ int32_t cube_batch_size(const cube_batch* b);
  * (state, density, power, ...) apply to it; stepping a box alone makes the batch refuse to step
  * until the boxes are at the same step again (CUBE_E_STATE). */
 cube_sim* cube_batch_box(cube_batch* b, int32_t i);
+/* How cube_batch_step launches the boxes' kernels: 0 (default) one captured graph per step for
+ * the whole ensemble; 1 each box's kernels enqueued directly on its own stream, box after box (no
+ * graph). Both give the same results. Errors: CUBE_E_INVALID. */
+int cube_batch_set_mode(cube_batch* b, int32_t mode);
 /* Initial conditions of every box (cube_init_ic on each). */
 int cube_batch_init_ic(cube_batch* b);
 /* cube_autotune on the first box of each distinct shape (mesh, lattice, codec); the choice is

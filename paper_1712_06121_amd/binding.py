@@ -27,11 +27,12 @@ SIGMA_GLOBAL, SIGMA_PER_CELL = 0, 1
 EXPORTED = [
     "cube_create", "cube_destroy", "cube_last_error", "cube_init_ic", "cube_load_particles", "cube_step",
     "cube_scale_factor", "cube_steps_done", "cube_num_particles", "cube_get_density", "cube_get_power",
-    "cube_get_state", "cube_set_state", "cube_stage_deposit", "cube_stage_solve", "cube_stage_move",
+    "cube_get_state", "cube_set_state", "cube_get_counts", "cube_stage_deposit", "cube_stage_solve", "cube_stage_move",
     "cube_get_mesh", "cube_set_mesh", "cube_get_ic_displacement", "cube_get_tables", "cube_get_schedule",
     "cube_device_bytes", "cube_set_profiling", "cube_get_timings", "cube_autotune", "cube_get_variant",
     "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
-    "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_footprint",
+    "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
+    "cube_footprint",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -120,6 +121,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
     lib.cube_get_state.argtypes = [sim_p, POINTER(CubeStateView)]
     lib.cube_set_state.argtypes = [sim_p, POINTER(CubeStateView)]
+    lib.cube_get_counts.argtypes = [sim_p, c_void_p]
     lib.cube_stage_move.argtypes = [sim_p, c_float, c_float]
     lib.cube_get_mesh.argtypes = [sim_p, c_void_p]
     lib.cube_set_mesh.argtypes = [sim_p, c_void_p]
@@ -146,6 +148,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("cube_batch_init_ic", "cube_batch_autotune"):
         getattr(lib, name).argtypes = [batch_p]
     lib.cube_batch_step.argtypes = [batch_p, c_int32]
+    lib.cube_batch_set_mode.argtypes = [batch_p, c_int32]
     lib.cube_footprint.argtypes = [POINTER(CubeParams)]
     lib.cube_footprint.restype = c_int64
     srv_p = c_void_p
@@ -321,6 +324,11 @@ class Sim:
         st["steps_done"] = view.steps_done
         return st
 
+    def get_counts(self) -> np.ndarray:
+        out = np.empty(self.nc**3, np.uint32)
+        self._check(self._lib.cube_get_counts(self._h, _ptr(out)))
+        return out
+
     def set_state(self, cnt, chi, nu, vc, vs, steps_done: int = 0):
         cnt = np.ascontiguousarray(cnt, np.uint32)
         chi = np.ascontiguousarray(chi, self.chi_dtype)
@@ -440,6 +448,11 @@ class Batch:
 
     def step(self, k: int = 1) -> int:
         return self._check(self._lib.cube_batch_step(self._h, k))
+
+    GRAPH, STREAMS = 0, 1
+
+    def set_mode(self, mode: int):
+        self._check(self._lib.cube_batch_set_mode(self._h, mode))
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -564,6 +564,16 @@ int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* 
   return CUBE_OK;
 }
 
+int cube_get_counts(cube_sim* sim, uint32_t* cnt) {
+  if (!sim || !cnt) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    CUBE_HIP(hipMemcpyAsync(cnt, s.cnt[s.cur], sizeof(uint32_t) * s.nc3, hipMemcpyDeviceToHost, s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+  });
+  return CUBE_OK;
+}
+
 int cube_get_state(cube_sim* sim, cube_state_view* out) {
   if (!sim || !out || !out->cnt || !out->chi || !out->nu || !out->vc || !out->vs) return CUBE_E_INVALID;
   cube::Sim& s = sim->s;

@@ -20,6 +20,7 @@ struct cube_batch {
   hipEvent_t fork = nullptr;
   hipStream_t main = nullptr;
   bool own_main = false;  // graphs cannot be captured on the null stream: the batch then makes its own
+  int mode = 0;           // 0: one captured graph per step; 1: kernels enqueued box by box on the box streams
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::string last_error;
@@ -338,6 +339,16 @@ cube_sim* cube_batch_box(cube_batch* b, int32_t i) {
   return b->boxes[i];
 }
 
+int cube_batch_set_mode(cube_batch* b, int32_t mode) {
+  if (!b) return CUBE_E_INVALID;
+  if (mode != 0 && mode != 1) {
+    b->last_error = "batch mode must be 0 (graph) or 1 (streams)";
+    return CUBE_E_INVALID;
+  }
+  b->mode = mode;
+  return CUBE_OK;
+}
+
 int cube_batch_init_ic(cube_batch* b) {
   if (!b) return CUBE_E_INVALID;
   for (size_t i = 0; i < b->boxes.size(); ++i) {
@@ -408,14 +419,25 @@ int cube_batch_step(cube_batch* b, int32_t k) {
         rc = CUBE_DONE;
         break;
       }
-      const int par = ss[0]->cur;
-      if (!b->exec[par]) cube::build_graph(*b, par);
-      CUBE_HIP(hipGraphLaunch(b->exec[par], b->main));
-      for (cube::Sim* s : ss) {
-        s->cur ^= 1;
-        s->steps_done++;
+      if (b->mode == 0) {
+        const int par = ss[0]->cur;
+        if (!b->exec[par]) cube::build_graph(*b, par);
+        CUBE_HIP(hipGraphLaunch(b->exec[par], b->main));
+        for (cube::Sim* s : ss) {
+          s->cur ^= 1;
+          s->steps_done++;
+        }
+      } else {
+        // one step of every box on its own stream: the hardware queues run them side by side
+        for (size_t bi = 0; bi < ss.size(); ++bi) cube::enqueue_graph_step(*ss[bi], b->streams[bi]);
+        for (cube::Sim* s : ss) s->steps_done++;  // launch_move flipped the parity already
       }
     }
+    if (b->mode != 0)
+      for (size_t bi = 0; bi < ss.size(); ++bi) {
+        CUBE_HIP(hipEventRecord(b->joins[bi], b->streams[bi]));
+        CUBE_HIP(hipStreamWaitEvent(b->main, b->joins[bi], 0));
+      }
     CUBE_HIP(hipStreamSynchronize(b->main));
     for (size_t i = 0; i < ss.size(); ++i) {
       try {

@@ -523,7 +523,7 @@ struct MoveLds {
   // moments: in LDS over the tile and its ring, flushed at the end; with the potential tile in LDS
   // (MODE 0) they go to the global accumulators directly, so that three workgroups fit a CU
   static constexpr bool kGlobalMom = MODE == 0;
-  static constexpr int kMom = kGlobalMom ? 1 : RC * 4;
+  static constexpr int kMom = kGlobalMom ? TC * 4 : RC * 4;  // own cells only, or tile and ring
 };
 
 // at least six wavefronts per SIMD (three 512-thread workgroups per CU): at most 80 VGPRs
@@ -541,8 +541,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) mcnt[i] = 0u;
-  if constexpr (!L::kGlobalMom)
-    for (int i = threadIdx.x; i < RC * 4; i += NTH) mom[i] = 0ull;
+  for (int i = threadIdx.x; i < L::kMom; i += NTH) mom[i] = 0ull;
   const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int c0, c1;
@@ -590,12 +589,20 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
     if (active && tail) {
       atomicAdd(&mcnt[key], (uint32_t)(lane - st + 1));
       if constexpr (L::kGlobalMom) {
-        const int gx = wrapi(g.cx0 - 1 + r % RG, a.nc), gy = wrapi(g.cy0 - 1 + (r / RG) % RG, a.nc);
-        const int gz = wrapi(g.cz0 - 1 + r / (RG * RG), a.nc);
-        const int64_t cn = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
+        // new cell inside the tile: the tile's LDS accumulators; in the ring: the global ones
+        const int rx = r % RG, ry = (r / RG) % RG, rz = r / (RG * RG);
+        if (rx >= 1 && rx <= T && ry >= 1 && ry <= T && rz >= 1 && rz <= T) {
+          const int so = (rx - 1) + T * ((ry - 1) + T * (rz - 1));
 #pragma unroll
-        for (int d = 0; d < 4; ++d)
-          atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
+          for (int d = 0; d < 4; ++d) atomicAdd(&mom[so * 4 + d], (unsigned long long)q[d]);
+        } else {
+          const int gx = wrapi(g.cx0 - 1 + rx, a.nc), gy = wrapi(g.cy0 - 1 + ry, a.nc);
+          const int gz = wrapi(g.cz0 - 1 + rz, a.nc);
+          const int64_t cn = gx + (int64_t)a.nc * (gy + (int64_t)a.nc * gz);
+#pragma unroll
+          for (int d = 0; d < 4; ++d)
+            atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
+        }
       } else {
 #pragma unroll
         for (int d = 0; d < 4; ++d) atomicAdd(&mom[r * 4 + d], (unsigned long long)q[d]);
@@ -608,7 +615,15 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
     const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
     a.mig[d * a.nc3 + c] = mcnt[i];
   }
-  if constexpr (!L::kGlobalMom) {
+  if constexpr (L::kGlobalMom) {
+    for (int i = threadIdx.x; i < TC * 4; i += NTH) {
+      const unsigned long long v = mom[i];
+      if (v == 0ull) continue;
+      const int so = i / 4, q = i % 4;
+      const int64_t c = (g.cx0 + so % T) + (int64_t)a.nc * ((g.cy0 + (so / T) % T) + (int64_t)a.nc * (g.cz0 + so / (T * T)));
+      atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[q * a.nc3 + c]), v);
+    }
+  } else {
     for (int i = threadIdx.x; i < RC * 4; i += NTH) {
       const unsigned long long v = mom[i];
       if (v == 0ull) continue;
@@ -843,6 +858,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   const BT* bucket;
   if constexpr (NNU == 1) bucket = bucket_lds;
   else bucket = a.tbucket;
+  // count pass: moments of the new cells inside the tile, flushed to the global accumulators at the end
+  __shared__ unsigned long long omom[SCATTER ? 1 : TC * 4];
+  if constexpr (!SCATTER)
+    for (int i = threadIdx.x; i < TC * 4; i += NTH) omom[i] = 0ull;
   // mean velocity and decode scale of the tile's cells
   __shared__ float4 cellv[TC];
   if (threadIdx.x < TC) {
@@ -870,11 +889,26 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const CT* chx = static_cast<const CT*>(a.chi) + base;
     const NT* nux = static_cast<const NT*>(a.nu) + base;
     const int64_t crow = (int64_t)a.nc * ((g.cy0 + o1) + (int64_t)a.nc * (g.cz0 + o2));
+    // the codes of the next chunk are loaded before this chunk's atomics and stores are issued, so
+    // waiting for them never waits for those (the vector memory counter is in order)
+    int chn[3] = {0, 0, 0}, nun[3] = {0, 0, 0};
+    auto load_chunk = [&](uint32_t jj) {
+      if (jj < nrow) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          chn[d] = (int)chx[d * a.cap + jj];
+          nun[d] = (int)nux[d * a.cap + jj];
+        }
+      }
+    };
+    load_chunk(lane);
     for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
       const uint32_t j = j0 + lane;
       const bool active = j < nrow;
       const int ci = (int)(j >= p1) + (int)(j >= p2) + (int)(j >= p3);  // cell of the row
       const int s = s0 + ci;
+      const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
+      if (j0 + 64 < nrow) load_chunk(j + 64);
       float v[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
       int ch[3] = {0, 0, 0};
       if (active) {
@@ -882,8 +916,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         const float vcv[3] = {cv.x, cv.y, cv.z};
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          ch[d] = (int)chx[d * a.cap + j];
-          int nuv = (int)nux[d * a.cap + j];
+          ch[d] = chc[d];
+          int nuv = nuc[d];
           nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
           l[d] = (float)(2 * ch[d] + 1) * unit;
           v[d] = vcv[d] + cv.w * tdec[nuv + a.vhalf];
@@ -956,21 +990,26 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           for (int d = 0; d < 4; ++d)
             tot[d] = read_lane_u64(ps[d], lb) - (la > 0 ? read_lane_u64(ps[d], la - 1) : 0ull);
           if (lane == 0) {
-            const int64_t c = (g.cx0 + cc) + crow;
             atomicAdd(&grp[(s0 + cc) * 27 + 13], (uint32_t)nst);
 #pragma unroll
-            for (int d = 0; d < 4; ++d)
-              atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + c]), tot[d]);
+            for (int d = 0; d < 4; ++d) atomicAdd(&omom[(s0 + cc) * 4 + d], tot[d]);
           }
         }
         if (active && !stay) {
           atomicAdd(&grp[s * 27 + dcode], 1u);
-          const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
-          const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
-          const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
+          // new cell inside the tile: the tile's LDS accumulators; in the ring: the global ones
+          const int tx = ci + k[0], ty = o1 + k[1], tz = o2 + k[2];
+          if (tx >= 0 && tx < T && ty >= 0 && ty < T && tz >= 0 && tz < T) {
+            const int so = tx + T * (ty + T * tz);
 #pragma unroll
-          for (int d = 0; d < 4; ++d)
-            atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
+            for (int d = 0; d < 4; ++d) atomicAdd(&omom[so * 4 + d], (unsigned long long)q[d]);
+          } else {
+            const int nx = wrapi(g.cx0 + tx, a.nc), ny = wrapi(g.cy0 + ty, a.nc), nz = wrapi(g.cz0 + tz, a.nc);
+            const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+              atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
+          }
         }
       } else {
         // lanes with the same (cell of the row, displacement): rank among them in storage order
@@ -1016,6 +1055,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const int s = i / 27, d = i % 27;
       const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
       a.mig[d * a.nc3 + c] = grp[i];
+    }
+    if (threadIdx.x < TC * 4) {
+      const int so = threadIdx.x / 4, d = threadIdx.x % 4;
+      const unsigned long long m = omom[threadIdx.x];
+      const int64_t c = (g.cx0 + so % T) + (int64_t)a.nc * ((g.cy0 + (so / T) % T) + (int64_t)a.nc * (g.cz0 + so / (T * T)));
+      if (m) atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + c]), m);
     }
   }
 }

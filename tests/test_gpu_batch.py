@@ -58,6 +58,21 @@ def test_batch_equals_each_box_alone(lib):
         assert_same(got[i], run_alone(lib, cfg, 7), f"box {i}")
 
 
+def test_batch_stream_mode_equals_alone(lib):
+    cfgs = small_ensemble()[:3]
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        b.set_mode(b.STREAMS)
+        b.step(2)
+        b.set_mode(b.GRAPH)  # the modes can be mixed: both keep the boxes at the same step
+        b.step(1)
+        b.set_mode(b.STREAMS)
+        b.step(2)
+        got = [box.get_state() for box in b.boxes]
+    for i, cfg in enumerate(cfgs):
+        assert_same(got[i], run_alone(lib, cfg, 5), f"box {i}")
+
+
 def test_batch_autotune_keeps_results(lib):
     cfgs = small_ensemble()[:3]
     with lib.Batch(cfgs) as b:
