@@ -127,6 +127,19 @@ int cube_get_density(cube_sim* sim, float* dst, int dst_on_device);
  * mean |k| (h/Mpc), mean P ((Mpc/h)^3, FP64 shell sums) and the number of modes. */
 int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* nmodes);
 
+/* Cross power spectrum of the current states of two simulations over the same box (Sec. 3,
+ * Eq. (cps) with two fields; the cross-correlation coefficient of Eq. (ccc) is
+ * pab / sqrt(paa pbb)). Both densities are CIC-deposited on their own meshes and transformed;
+ * shells as in cube_get_power, n = 1 .. nbins, nbins <= nm/2 of the smaller mesh. Meshes of one
+ * size use every mode; meshes of different sizes use the modes whose every integer component
+ * has |n_i| < nm/2 of the smaller mesh (its Nyquist planes are aliased). Host outputs of length
+ * nbins: mean |k|, P_aa, P_bb, P_ab and the number of modes. `a` and `b` may be the same
+ * simulation; two simulations must be on one device (their streams are ordered by an event) and
+ * have equal box sizes. Errors are reported on `a`: CUBE_E_INVALID, CUBE_E_STATE, CUBE_E_HIP.
+ * Overwrites both meshes (scratch between steps). */
+int cube_get_cross_power(cube_sim* a, cube_sim* b, int32_t nbins, double* k, double* paa, double* pbb,
+                         double* pab, double* nmodes);
+
 /* Checkpoint, the paper's "disjoint state" {rho_c, v_c, chi, nu} (Sec. 2.3.1): host buffers.
  * cnt: nc^3 uint32; chi: 3 planes of n codes (uint8 chi+128 for x_bytes 1, uint16 chi+32768
  * for 2); nu: 3 planes of n codes (int8 or int16); vc: 3 planes of nc^3 FP32; vs: nc^3 FP32

@@ -32,7 +32,7 @@ EXPORTED = [
     "cube_device_bytes", "cube_set_profiling", "cube_get_timings", "cube_autotune", "cube_get_variant",
     "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
-    "cube_footprint",
+    "cube_footprint", "cube_get_cross_power",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_num_particles.restype = c_int64
     lib.cube_get_density.argtypes = [sim_p, c_void_p, c_int]
     lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.cube_get_cross_power.argtypes = [sim_p, sim_p, c_int32] + [c_void_p] * 5
     lib.cube_get_state.argtypes = [sim_p, POINTER(CubeStateView)]
     lib.cube_set_state.argtypes = [sim_p, POINTER(CubeStateView)]
     lib.cube_get_counts.argtypes = [sim_p, c_void_p]
@@ -312,6 +313,14 @@ class Sim:
         k, pk, nm = (np.empty(nb) for _ in range(3))
         self._check(self._lib.cube_get_power(self._h, nb, _ptr(k), _ptr(pk), _ptr(nm)))
         return k, pk, nm
+
+    def get_cross_power(self, other: "Sim", nbins: int | None = None):
+        """(k, P_aa, P_bb, P_ab, n_modes) of this state (a) and `other` (b) over the same box; the
+        cross-correlation coefficient is P_ab / sqrt(P_aa P_bb)."""
+        nb = nbins or min(self.nm, other.nm) // 2
+        out = [np.empty(nb) for _ in range(5)]
+        self._check(self._lib.cube_get_cross_power(self._h, other._h, nb, *(_ptr(x) for x in out)))
+        return tuple(out)
 
     def get_state(self) -> dict:
         n = self.n

@@ -236,7 +236,7 @@ int64_t footprint_bytes(const cube_params& p) {
   auto field = [](int64_t n) { return n * n * (n / 2 + (n >= 1024 ? 8 : 16)) * 2 * (int64_t)sizeof(float); };
   int64_t b = 2 * (pb + 4 * nc3 + 8 * (nc3 + 1) + 12 * nc3 + 4 * nc3);  // state, double buffered
   b += 4 * nc3 + 2 * 108 * nc3 + 32 * nc3 + 8 * nc3;                  // vinv, mig, slot, mom, dev
-  b += 24 * ((nc3 + 255) / 256) + 64 + 16 + 24 * (nm / 2 + 1);       // link blocks, scalars, flags, P(k)
+  b += 24 * ((nc3 + 255) / 256) + 64 + 16 + 40 * (nm / 2 + 1);       // link blocks, scalars, flags, P(k)
   b += 12 * nm + (np != nm ? 12 * np : 0) + field(nm);               // FFT plans and the mesh
   const int64_t m = ((int64_t)1 << (8 * p.v_bytes)) - 1;
   b += 4 * m + 4 * (m - 1) + 2 * 4 * (m + 1);                         // codec tables
@@ -336,7 +336,7 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
     s.blk_off = static_cast<uint64_t*>(s.dmalloc(sizeof(uint64_t) * s.nblk));
     s.scal = static_cast<double*>(s.dmalloc(sizeof(double) * 8));
     s.flags = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * 4));
-    s.pk_acc = static_cast<double*>(s.dmalloc(sizeof(double) * 3 * (s.nm / 2 + 1)));
+    s.pk_acc = static_cast<double*>(s.dmalloc(sizeof(double) * 5 * (s.nm / 2 + 1)));
     cube::fft_plan_create(s, s.mesh_plan, s.nm);
     if (s.np == s.nm) s.lat_plan = s.mesh_plan;
     else cube::fft_plan_create(s, s.lat_plan, s.np);
@@ -559,6 +559,58 @@ int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* 
       nmodes[b - 1] = w;
       k[b - 1] = w > 0 ? kf * acc[nb + b] / w : 0.0;
       pk[b - 1] = w > 0 ? (L * L * L / nm6) * acc[b] / w : 0.0;
+    }
+  });
+  return CUBE_OK;
+}
+
+int cube_get_cross_power(cube_sim* sa, cube_sim* sb, int32_t nbins, double* k, double* paa, double* pbb,
+                         double* pab, double* nmodes) {
+  if (!sa || !sb || !k || !paa || !pbb || !pab || !nmodes) return CUBE_E_INVALID;
+  cube::Sim& a = sa->s;
+  cube::Sim& b = sb->s;
+  const int n = std::min(a.nm, b.nm);
+  if (a.p.box != b.p.box) return cube::fail(sa, Error{CUBE_E_INVALID, "the two simulations have different box sizes"});
+  if (nbins < 1 || nbins > n / 2)
+    return cube::fail(sa, Error{CUBE_E_INVALID, "nbins must be in [1, nm/2] of the smaller mesh"});
+  CUBE_GUARD(sa, {
+    cube::require_particles(a);
+    cube::require_particles(b);
+    if (sa != sb) {
+      hipPointerAttribute_t pa{}, pb{};
+      CUBE_HIP(hipPointerGetAttributes(&pa, a.mesh));
+      CUBE_HIP(hipPointerGetAttributes(&pb, b.mesh));
+      if (pa.device != pb.device) throw Error{CUBE_E_INVALID, "the two simulations live on different devices"};
+    }
+    const int nsh = n / 2 + 1;
+    cube::launch_deposit(a, a.stream);
+    cube::fft_forward_3d(a.mesh_plan, a.mesh, a.stream);
+    if (sa != sb) {
+      cube::launch_deposit(b, b.stream);
+      cube::fft_forward_3d(b.mesh_plan, b.mesh, b.stream);
+      if (b.stream != a.stream) {
+        hipEvent_t done;
+        CUBE_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(done, b.stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(a.stream, done, 0);
+        hipEventDestroy(done);
+        CUBE_HIP(e);
+      }
+    }
+    CUBE_HIP(hipMemsetAsync(a.pk_acc, 0, sizeof(double) * 5 * nsh, a.stream));
+    cube::cross_shells(a.mesh_plan, a.mesh, b.mesh_plan, b.mesh, a.pk_acc, a.stream);
+    std::vector<double> acc(5 * nsh);
+    CUBE_HIP(hipMemcpyAsync(acc.data(), a.pk_acc, sizeof(double) * 5 * nsh, hipMemcpyDeviceToHost, a.stream));
+    CUBE_HIP(hipStreamSynchronize(a.stream));
+    const double L = a.p.box, kf = 2.0 * M_PI / L, v = L * L * L;
+    const double na3 = std::pow((double)a.nm, 3), nb3 = std::pow((double)b.nm, 3);
+    for (int m = 1; m <= nbins; ++m) {
+      const double w = acc[4 * nsh + m];
+      nmodes[m - 1] = w;
+      k[m - 1] = w > 0 ? kf * acc[3 * nsh + m] / w : 0.0;
+      pab[m - 1] = w > 0 ? v / (na3 * nb3) * acc[m] / w : 0.0;
+      paa[m - 1] = w > 0 ? v / (na3 * na3) * acc[nsh + m] / w : 0.0;
+      pbb[m - 1] = w > 0 ? v / (nb3 * nb3) * acc[2 * nsh + m] / w : 0.0;
     }
   });
   return CUBE_OK;

@@ -111,7 +111,7 @@ struct Sim {
   int vm = 255;
 
   // power spectrum accumulators
-  double* pk_acc = nullptr;  // 3 x (nm/2 + 1)
+  double* pk_acc = nullptr;  // 5 x (nm/2 + 1): auto (3 rows) or cross (5 rows) shell sums
 
   // schedule
   Cosmo cosmo{};
@@ -156,6 +156,9 @@ void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st);
 // evs (optional): 6 events recorded before the first pass and after each of the five passes
 void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs = nullptr);
 void fft_power(const FFTPlan& pl, float* data, double* acc, hipStream_t st);
+// shell sums of two forward-transformed meshes over one box: 5 x (n/2 + 1) doubles, n the smaller size
+void cross_shells(const FFTPlan& pa, const float* a, const FFTPlan& pb, const float* b, double* acc,
+                  hipStream_t st);
 // initial conditions: psi_d = IFFT( i n_d tab[|n|^2] W ) with W the transformed noise
 void fft_ic_component(const FFTPlan& pl, const float* wk, float* out, const float* tab, int dim,
                       hipStream_t st);

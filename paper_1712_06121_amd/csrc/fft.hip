@@ -557,6 +557,76 @@ void ic_n(const FFTPlan& pl, const float* wk, float* out, const float* tab, int 
 
 }  // namespace
 
+// Cross power of two density meshes over one box (Sec. 3, Eqs. (cps) and (ccc)): per shell m of the
+// smaller mesh (size n), the sums over its modes of w Re(conj(a_k) b_k), w |a_k|^2, w |b_k|^2, w |k|
+// and w (w = 1 on the x = 0 and x = n/2 planes, 2 elsewhere: the conjugate half). Each mode is read
+// from both half spectra at its own indices. Meshes of one size contribute every mode; of two
+// sizes, the modes with every |f_i| < n/2 (the smaller mesh's Nyquist planes are aliased there).
+struct CrossArgs {
+  const float2* a;
+  const float2* b;
+  int64_t pa, pb;  // complex values per row
+  int na, nb, n;   // mesh sizes, the smaller one
+  int all;         // 1: one size, every mode
+  double* acc;     // 5 x (n/2 + 1): P_ab, P_aa, P_bb, |n|, weight
+};
+
+// one workgroup per z index of the smaller mesh
+__global__ __launch_bounds__(1024) void k_cross_shells(CrossArgs c) {
+  extern __shared__ double sacc[];
+  const int half = c.n / 2, nsh = half + 1;
+  for (int i = threadIdx.x; i < 5 * nsh; i += blockDim.x) sacc[i] = 0.0;
+  __syncthreads();
+  const int iz = blockIdx.x;
+  const int fz = signed_freq(iz, c.n);
+  const bool zok = c.all || (fz != half);
+  const int nx = c.all ? half + 1 : half;
+  const int64_t rows = zok ? (int64_t)c.n * nx : 0;
+  const int za = fz < 0 ? fz + c.na : fz, zb = fz < 0 ? fz + c.nb : fz;
+  for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) {
+    const int iy = (int)(i / nx), fx = (int)(i % nx);
+    const int fy = signed_freq(iy, c.n);
+    if (!c.all && fy == half) continue;
+    const int n2 = fx * fx + fy * fy + fz * fz;
+    if (n2 == 0) continue;
+    int m = (int)sqrtf((float)n2);
+    while ((2 * m + 1) * (2 * m + 1) <= 4 * n2) ++m;
+    while (m > 0 && (2 * m - 1) * (2 * m - 1) > 4 * n2) --m;
+    if (m < 1 || m > half) continue;
+    const int ya = fy < 0 ? fy + c.na : fy, yb = fy < 0 ? fy + c.nb : fy;
+    const float2 u = c.a[((int64_t)za * c.na + ya) * c.pa + fx];
+    const float2 v = c.b[((int64_t)zb * c.nb + yb) * c.pb + fx];
+    const double w = (fx == 0 || fx == half) ? 1.0 : 2.0;
+    atomicAdd(&sacc[m], w * ((double)u.x * v.x + (double)u.y * v.y));
+    atomicAdd(&sacc[nsh + m], w * ((double)u.x * u.x + (double)u.y * u.y));
+    atomicAdd(&sacc[2 * nsh + m], w * ((double)v.x * v.x + (double)v.y * v.y));
+    atomicAdd(&sacc[3 * nsh + m], w * sqrt((double)n2));
+    atomicAdd(&sacc[4 * nsh + m], w);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 5 * nsh; i += blockDim.x) {
+    const double x = sacc[i];
+    if (x != 0.0) atomicAdd(&c.acc[i], x);
+  }
+}
+
+void cross_shells(const FFTPlan& pa, const float* a, const FFTPlan& pb, const float* b, double* acc,
+                  hipStream_t st) {
+  CrossArgs c;
+  c.a = reinterpret_cast<const float2*>(a);
+  c.b = reinterpret_cast<const float2*>(b);
+  c.pa = pa.pitch_c;
+  c.pb = pb.pitch_c;
+  c.na = pa.n;
+  c.nb = pb.n;
+  c.n = std::min(pa.n, pb.n);
+  c.all = pa.n == pb.n;
+  c.acc = acc;
+  const size_t lds = sizeof(double) * 5 * (c.n / 2 + 1);
+  k_cross_shells<<<c.n, 1024, lds, st>>>(c);
+  CUBE_HIP(hipGetLastError());
+}
+
 bool fft_size_supported(int n) {
   switch (n) {
     case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 1024: case 2048:

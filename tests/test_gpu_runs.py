@@ -133,6 +133,70 @@ def test_power_estimator_matches_oracle_on_same_density(Sim):
     assert np.allclose(pk, p0, rtol=2e-4)
 
 
+def _twin_delta(st, cfg):
+    tw = twin_state(st, cfg)
+    return twin.delta_from_rho(twin.deposit_int(tw, cfg["nm_side"]), tw.n, tw.nchi).astype(np.float64)
+
+
+@pytest.mark.parametrize("nm_b", [64, 128])
+def test_cross_power_matches_oracle_on_same_densities(Sim, nm_b):
+    """x1v1 against x2v2 from the same initial conditions, after 20 steps; the second run on the
+    same mesh or on one of twice the size (the common modes only)."""
+    cfg_a = synth.WORKLOADS["c1_pm32"]
+    cfg_b = dict(cfg_a, x_bytes=2, v_bytes=2, nm_side=nm_b, nc_side=nm_b // 4)
+    with Sim(**cfg_a) as a, Sim(**cfg_b) as b:
+        a.init_ic()
+        b.init_ic()
+        a.step(20)
+        b.step(20)
+        k, paa, pbb, pab, nmodes = a.get_cross_power(b)
+        sa, sb = a.get_state(), b.get_state()
+    k0, paa0, pbb0, pab0, n0 = power.cross_spectrum(_twin_delta(sa, cfg_a), _twin_delta(sb, cfg_b), cfg_a["box"])
+    assert len(k) == 32 and np.array_equal(nmodes, n0)
+    assert np.allclose(k, k0, rtol=1e-12)
+    assert np.allclose(paa, paa0, rtol=2e-4) and np.allclose(pbb, pbb0, rtol=2e-4)
+    assert np.all(np.abs(pab - pab0) <= 2e-4 * np.sqrt(paa0 * pbb0))
+    xi = power.correlation(paa, pbb, pab)
+    print(f"nm_b {nm_b}: xi at shells 1..8 {np.round(xi[:8], 5)}")
+    # measured: one mesh 1 - xi < 1.1e-3 over shells 1..8; twice the mesh (a different force
+    # resolution, the paper's PM decorrelation) 2e-2 at shell 8
+    assert np.all(xi[:4] > 0.99)
+
+
+def test_cross_power_of_a_state_with_itself(Sim):
+    cfg = synth.WORKLOADS["c1_pm32"]
+    with Sim(**cfg) as sim:
+        sim.init_ic()
+        sim.step(5)
+        k, pk, n = sim.get_power()
+        kx, paa, pbb, pab, nx = sim.get_cross_power(sim)
+        with pytest.raises(Exception) as e:
+            with Sim(**dict(cfg, box=120.0)) as other:
+                other.init_ic()
+                sim.get_cross_power(other)
+        assert "box" in str(e.value)
+    assert np.array_equal(n, nx) and np.allclose(k, kx, rtol=1e-12)
+    assert np.allclose(paa, pk, rtol=1e-6) and np.allclose(paa, pbb, rtol=1e-12)  # atomics: any order
+    assert np.allclose(pab, paa, rtol=1e-12)
+
+
+def test_full_run_x1v1_correlates_with_x2v2(Sim):
+    """The paper's accuracy claim in cross-correlation form (Sec. 3, Eq. (ccc)): a full x1v1 run
+    stays correlated with x2v2 from the same initial conditions at k < 0.2 k_Nyquist."""
+    cfg_a = synth.WORKLOADS["c1_pm32"]
+    cfg_b = dict(cfg_a, x_bytes=2, v_bytes=2)
+    with Sim(**cfg_a) as a, Sim(**cfg_b) as b:
+        a.init_ic()
+        b.init_ic()
+        a.step(cfg_a["n_steps"])
+        b.step(cfg_b["n_steps"])
+        k, paa, pbb, pab, nmodes = a.get_cross_power(b)
+    xi = power.correlation(paa, pbb, pab)
+    kny = np.pi * cfg_a["nm_side"] / cfg_a["box"]
+    print(f"1 - xi: k<0.2k_Ny {np.round(1 - xi[k < 0.2 * kny], 5)}; k<k_Ny/2 max {np.max(1 - xi[k < kny / 2]):.4f}")
+    assert np.all(xi[k < 0.2 * kny] > 0.99)
+
+
 def _full_run_power(Sim, name, nbins=None):
     cfg = synth.WORKLOADS[name]
     with Sim(**cfg) as sim:

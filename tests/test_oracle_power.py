@@ -38,3 +38,72 @@ def test_mode_counts():
     b = np.floor(np.sqrt(n2) + 0.5)
     expect = np.array([(b == s).sum() for s in range(1, nm // 2 + 1)])
     assert np.array_equal(nmodes, expect)
+
+
+def _grid(nm):
+    i = np.arange(nm)
+    return np.meshgrid(i, i, i, indexing="ij")  # z, y, x
+
+
+def test_cross_of_a_field_with_itself_and_its_negative():
+    g = np.random.default_rng(7)
+    delta = g.normal(size=(32, 32, 32))
+    k, paa, pbb, pab, nmodes = power.cross_spectrum(delta, delta, 80.0)
+    assert np.allclose(paa, pbb, rtol=0) and np.allclose(pab, paa, rtol=1e-12)
+    assert np.allclose(power.correlation(paa, pbb, pab), 1.0, rtol=1e-12)
+    _, _, _, pneg, _ = power.cross_spectrum(delta, -delta, 80.0)
+    assert np.allclose(power.correlation(paa, pbb, pneg), -1.0, rtol=1e-12)
+
+
+@pytest.mark.parametrize("theta", [0.3, 1.2, 2.5])
+def test_cross_of_phase_shifted_cosines_is_cos_theta(theta):
+    nm, box, amp = 32, 60.0, 0.2
+    z, y, x = _grid(nm)
+    ph = 2 * np.pi * (2 * x - 5 * y + 3 * z) / nm  # |n|^2 = 38: shell 6
+    a = amp * np.cos(ph)
+    b = amp * np.cos(ph + theta)
+    k, paa, pbb, pab, nmodes = power.cross_spectrum(a, b, box)
+    live = np.nonzero(paa * nmodes > 1e-20)[0]
+    assert live.tolist() == [5]
+    # all of <a^2> L^3 sits in the one shell; the cross power carries cos(theta) of it
+    assert (paa * nmodes).sum() == pytest.approx(amp**2 / 2 * box**3, rel=1e-12)
+    assert (pab * nmodes).sum() == pytest.approx(np.cos(theta) * amp**2 / 2 * box**3, rel=1e-10)
+    assert power.correlation(paa, pbb, pab)[5] == pytest.approx(np.cos(theta), rel=1e-10)
+
+
+def test_cross_of_independent_noise_is_zero_within_scatter():
+    g = np.random.default_rng(8)
+    a, b = g.normal(size=(2, 48, 48, 48))
+    k, paa, pbb, pab, nmodes = power.cross_spectrum(a, b, 100.0)
+    xi = power.correlation(paa, pbb, pab)
+    sel = nmodes > 100
+    assert np.all(np.abs(xi[sel]) < 5 / np.sqrt(nmodes[sel]))
+
+
+def test_cross_between_mesh_sizes_uses_the_common_modes():
+    box, amp = 70.0, 0.1
+    waves = [(3, -5, 2), (-1, 4, 6), (7, 0, -3)]  # (n_x, n_y, n_z), every |n_i| < 8
+
+    def field(nm):
+        z, y, x = _grid(nm)
+        return sum(amp * np.cos(2 * np.pi * (nx * x + ny * y + nz * z) / nm + 0.4 * j)
+                   for j, (nx, ny, nz) in enumerate(waves))
+
+    a, b = field(16), field(32)
+    k, paa, pbb, pab, nmodes = power.cross_spectrum(a, b, box)
+    assert len(k) == 8
+    shells = sorted({int(np.floor(np.sqrt(nx * nx + ny * ny + nz * nz) + 0.5)) for nx, ny, nz in waves})
+    live = np.nonzero(paa * nmodes > 1e-20)[0] + 1
+    assert live.tolist() == shells
+    for p in (paa, pbb, pab):  # the same band-limited field on both meshes: one spectrum
+        assert (p * nmodes).sum() == pytest.approx(len(waves) * amp**2 / 2 * box**3, rel=1e-10)
+    assert np.allclose(power.correlation(paa, pbb, pab)[live - 1], 1.0, rtol=1e-10)
+    # the mode counts: integer vectors with every |n_i| < 8, shell floor(|n| + 1/2), brute force
+    f = np.arange(-7, 8)
+    n2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2
+    sh = np.floor(np.sqrt(n2) + 0.5)
+    assert np.array_equal(nmodes, [(sh == s).sum() for s in range(1, 9)])
+    # a scaled copy on the same mesh size keeps xi = 1 and scales P_ab linearly
+    _, _, _, pab2, _ = power.cross_spectrum(field(16), 3.0 * field(16), box)
+    _, p16, _, _, _ = power.cross_spectrum(field(16), field(16), box)
+    assert np.allclose(pab2, 3.0 * p16, rtol=1e-12)
