@@ -161,6 +161,21 @@ int cube_get_state(cube_sim* sim, cube_state_view* out);
 int cube_get_counts(cube_sim* sim, uint32_t* cnt);
 int cube_set_state(cube_sim* sim, const cube_state_view* in);
 
+/* Particle IDs, the optional I_P array of Sec. 2.1: one pid_bytes-byte unsigned integer per
+ * particle (4 or 8; 0 frees them), stored in the same order as chi and nu and carried through
+ * every step, half drift and re-sort. IDs are assigned as follows: cube_init_ic gives each particle
+ * its lattice index x + np (y + np z) (so its Lagrangian position q follows from the ID);
+ * cube_load_particles gives the index in the input arrays; cube_set_state, and
+ * cube_enable_pids when particles already exist, give 0 .. n-1 in storage order.
+ * pid_bytes 4 needs capacity <= 2^32. Adds 2 x pid_bytes x capacity bytes of device memory (both
+ * state buffers), which cube_footprint does not count. Errors: CUBE_E_INVALID, CUBE_E_NOMEM. */
+int cube_enable_pids(cube_sim* sim, int32_t pid_bytes);
+/* The n IDs of the current state in storage order (host memory, pid_bytes each), the checkpoint's
+ * I_P; cube_set_pids writes them back after cube_set_state. Errors: CUBE_E_STATE when IDs are
+ * not enabled or no particles exist. */
+int cube_get_pids(cube_sim* sim, void* host_dst);
+int cube_set_pids(cube_sim* sim, const void* host_src);
+
 /* ---- stages of one step, for parity checks and profiling -------------------------------- */
 
 /* CIC deposit of the current state into the mesh: delta in FP32 (exact integer accumulation,

@@ -20,7 +20,8 @@ codec       FP64 reference of the storage formats: Eqs. (chi), (x), (nu), (v); c
 twin        FP32 step-by-step reference of the compressed step (load-encode, integer CIC,
             move from a given potential, per-cell moments, counting-sort order): the part
             the GPU must reproduce bit-exactly from identical inputs.
-power       Auto power spectrum estimator, Eq. (cps) and Delta^2(k) (Sec. 3).
+power       Auto and cross power spectra, Eqs. (cps), (ccc) and Delta^2(k) (Sec. 3).
+displacement  Offsets of the same particle between two runs, Eq. (offset) (Sec. 3).
 ewald       Periodic direct-sum (Ewald) forces for a handful of particles.
 zeldovich   Exact 1-D Zel'dovich plane wave before shell crossing.
 memory      Memory model of Sec. 2.4, Eqs. (npmax)-(Mp_fine) and Table t.memory.

@@ -32,7 +32,7 @@ EXPORTED = [
     "cube_device_bytes", "cube_set_profiling", "cube_get_timings", "cube_autotune", "cube_get_variant",
     "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
-    "cube_footprint", "cube_get_cross_power",
+    "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -120,6 +120,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_get_density.argtypes = [sim_p, c_void_p, c_int]
     lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
     lib.cube_get_cross_power.argtypes = [sim_p, sim_p, c_int32] + [c_void_p] * 5
+    lib.cube_enable_pids.argtypes = [sim_p, c_int32]
+    lib.cube_get_pids.argtypes = [sim_p, c_void_p]
+    lib.cube_set_pids.argtypes = [sim_p, c_void_p]
     lib.cube_get_state.argtypes = [sim_p, POINTER(CubeStateView)]
     lib.cube_set_state.argtypes = [sim_p, POINTER(CubeStateView)]
     lib.cube_get_counts.argtypes = [sim_p, c_void_p]
@@ -228,6 +231,7 @@ class Sim:
         self.params = make_params(np_side, nm_side, box, nc_side, x_bytes, v_bytes, sigma_mode, omega_m, omega_l, h,
                                   sigma8, n_s, a_init, a_final, n_steps, spacing, seed, capacity)
         self._set_shape(self.params)
+        self.pid_bytes = 0
         self._owned = _handle is None
         if _handle is not None:  # a box owned by a Batch
             self._h = _handle
@@ -313,6 +317,23 @@ class Sim:
         k, pk, nm = (np.empty(nb) for _ in range(3))
         self._check(self._lib.cube_get_power(self._h, nb, _ptr(k), _ptr(pk), _ptr(nm)))
         return k, pk, nm
+
+    def enable_pids(self, pid_bytes: int = 8):
+        """Carry a particle ID of pid_bytes (4 or 8; 0 drops them) through every step."""
+        self._check(self._lib.cube_enable_pids(self._h, pid_bytes))
+        self.pid_bytes = pid_bytes
+
+    def get_pids(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.uint64 if self.pid_bytes == 8 else np.uint32)
+        self._check(self._lib.cube_get_pids(self._h, _ptr(out)))
+        return out
+
+    def set_pids(self, ids):
+        dt = np.uint64 if self.pid_bytes == 8 else np.uint32
+        ids = np.ascontiguousarray(ids, dtype=dt)
+        if ids.shape != (self.n,):
+            raise ValueError(f"expected {self.n} IDs")
+        self._check(self._lib.cube_set_pids(self._h, _ptr(ids)))
 
     def get_cross_power(self, other: "Sim", nbins: int | None = None):
         """(k, P_aa, P_bb, P_ab, n_modes) of this state (a) and `other` (b) over the same box; the

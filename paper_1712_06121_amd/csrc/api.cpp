@@ -684,6 +684,59 @@ int cube_set_state(cube_sim* sim, const cube_state_view* in) {
     s.have_particles = true;
     s.steps_done = in->steps_done < 0 ? 0 : (in->steps_done > s.p.n_steps ? s.p.n_steps : in->steps_done);
     s.half_drift_done = s.steps_done > 0;
+    cube::launch_pid_iota(s, st);
+    CUBE_HIP(hipStreamSynchronize(st));
+  });
+  return CUBE_OK;
+}
+
+int cube_enable_pids(cube_sim* sim, int32_t pid_bytes) {
+  if (!sim) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  if (pid_bytes != 0 && pid_bytes != 4 && pid_bytes != 8)
+    return cube::fail(sim, Error{CUBE_E_INVALID, "pid_bytes must be 0, 4 or 8"});
+  CUBE_GUARD(sim, {
+    if (pid_bytes == 4 && s.capacity > ((int64_t)1 << 32))
+      throw Error{CUBE_E_INVALID, "4-byte particle IDs need a capacity of at most 2^32"};
+    if (pid_bytes != s.pid_bytes) {
+      CUBE_HIP(hipStreamSynchronize(s.stream));
+      for (int b = 0; b < 2; ++b) {
+        if (s.pid[b]) s.dfree(s.pid[b]);
+        s.pid[b] = nullptr;
+      }
+      s.pid_bytes = 0;
+      s.config_gen++;
+      if (pid_bytes) {
+        for (int b = 0; b < 2; ++b) s.pid[b] = s.dmalloc((size_t)pid_bytes * (size_t)(s.capacity > 0 ? s.capacity : 1));
+        s.pid_bytes = pid_bytes;
+        if (s.have_particles) cube::launch_pid_iota(s, s.stream);
+        CUBE_HIP(hipStreamSynchronize(s.stream));
+      }
+    }
+  });
+  return CUBE_OK;
+}
+
+int cube_get_pids(cube_sim* sim, void* host_dst) {
+  if (!sim || !host_dst) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    if (!s.pid_bytes) throw Error{CUBE_E_STATE, "particle IDs are not enabled (cube_enable_pids)"};
+    cube::require_particles(s);
+    CUBE_HIP(hipMemcpyAsync(host_dst, s.pid[s.cur], (size_t)s.pid_bytes * s.n, hipMemcpyDeviceToHost, s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+  });
+  return CUBE_OK;
+}
+
+int cube_set_pids(cube_sim* sim, const void* host_src) {
+  if (!sim || !host_src) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    if (!s.pid_bytes) throw Error{CUBE_E_STATE, "particle IDs are not enabled (cube_enable_pids)"};
+    cube::require_particles(s);
+    CUBE_HIP(hipMemcpyAsync(s.pid[s.cur], host_src, (size_t)s.pid_bytes * s.n, hipMemcpyHostToDevice, s.stream));
+    CUBE_HIP(hipStreamSynchronize(s.stream));
   });
   return CUBE_OK;
 }

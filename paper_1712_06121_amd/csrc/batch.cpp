@@ -23,6 +23,7 @@ struct cube_batch {
   int mode = 0;           // 0: one captured graph per step; 1: kernels enqueued box by box on the box streams
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<int> gens;  // each box's config_gen when the graphs were captured
   std::string last_error;
 };
 
@@ -87,10 +88,21 @@ void build_graph(cube_batch& b, int par) {
   CUBE_HIP(hipGraphInstantiate(&b.exec[par], b.graph[par], nullptr, nullptr, 0));
 }
 
+// drop captured graphs that a later change of a box (variants, particle IDs) has made stale
+void check_graphs(cube_batch& b) {
+  std::vector<int> now(b.boxes.size());
+  for (size_t i = 0; i < b.boxes.size(); ++i) now[i] = b.boxes[i]->s.config_gen;
+  if (now != b.gens) {
+    destroy_graphs(b);
+    b.gens = now;
+  }
+}
+
 // z layout of the solve: 1 allocates the scratch copy (one mesh-sized buffer) if needed, 0 keeps
 // any allocated scratch, -1 selects 0 and frees the scratch
 void set_z_layout(Sim& s, int layout) {
   FFTPlan& pl = s.mesh_plan;
+  s.config_gen++;
   if (layout == 1 && !pl.zscratch) pl.zscratch = static_cast<float2*>(s.dmalloc(pl.field_floats() * sizeof(float)));
   if (layout < 0 && pl.zscratch) {
     s.dfree(pl.zscratch);
@@ -264,6 +276,7 @@ int cube_set_variant(cube_sim* sim, const cube_variant* v) {
     s.last_error = e.msg;
     return e.code;
   }
+  s.config_gen++;  // captured step graphs hold the previous kernels and buffers
   s.move_variant = v->move_variant;
   s.mesh_plan.colbx = v->fft_col_width;
   s.mesh_plan.zorder = v->fft_z_order;
@@ -420,6 +433,7 @@ int cube_batch_step(cube_batch* b, int32_t k) {
         break;
       }
       if (b->mode == 0) {
+        cube::check_graphs(*b);
         const int par = ss[0]->cur;
         if (!b->exec[par]) cube::build_graph(*b, par);
         CUBE_HIP(hipGraphLaunch(b->exec[par], b->main));

@@ -82,7 +82,10 @@ struct Sim {
   uint64_t* off[2] = {nullptr, nullptr};  // nc3 + 1 (exclusive prefix, last = N)
   float* vc[2] = {nullptr, nullptr};      // 3 x nc3
   float* vs[2] = {nullptr, nullptr};      // nc3 decode scale
+  void* pid[2] = {nullptr, nullptr};      // capacity particle IDs of pid_bytes each (optional)
+  int pid_bytes = 0;
   int cur = 0;
+  int config_gen = 0;  // bumped whenever captured step graphs of this simulation become stale
 
   // move scratch
   float* vinv = nullptr;       // nc3 encode scale 1/(sigma sqrt(2/pi))
@@ -171,6 +174,8 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
                  hipEvent_t* evs, bool dev_sched = false);
 void launch_advance_step(Sim& s, hipStream_t st);
 void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream_t st);
+// particle IDs 0 .. n-1 in storage order (when IDs are enabled)
+void launch_pid_iota(Sim& s, hipStream_t st);
 void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmodes);
 
 }  // namespace cube

@@ -244,7 +244,30 @@ struct MoveArgs {
   // step j = *kstep are kd[2 j] and kd[2 j + 1] instead of kf and df
   const float* kd;
   const int* kstep;
+  // particle IDs (Sec. 2.1): pid_bytes 0 (none), 4 or 8; stored in the order of chi and nu
+  const void* pid;
+  void* pid_n;
+  int pid_bytes;
 };
+
+// the ID of the particle at storage index p (steps), or of lattice particle li of tile cell s
+// (initial conditions: the lattice index x + N_p (y + N_p z))
+template <int MODE>
+__device__ __forceinline__ uint64_t particle_id(const MoveArgs& a, const TileGeom& g, int s, int64_t p, uint32_t li) {
+  if constexpr (MODE == 2) {
+    const int64_t gx = (int64_t)(g.cx0 + s % T) * a.q + li % a.q;
+    const int64_t gy = (int64_t)(g.cy0 + (s / T) % T) * a.q + (li / a.q) % a.q;
+    const int64_t gz = (int64_t)(g.cz0 + s / (T * T)) * a.q + li / (a.q * a.q);
+    return (uint64_t)(gx + a.np * (gy + a.np * gz));
+  } else {
+    return a.pid_bytes == 8 ? static_cast<const uint64_t*>(a.pid)[p] : static_cast<const uint32_t*>(a.pid)[p];
+  }
+}
+
+__device__ __forceinline__ void store_id(const MoveArgs& a, uint64_t dst, uint64_t id) {
+  if (a.pid_bytes == 8) static_cast<uint64_t*>(a.pid_n)[dst] = id;
+  else static_cast<uint32_t*>(a.pid_n)[dst] = (uint32_t)id;
+}
 
 // the kick/drift factors of this launch
 __device__ __forceinline__ void resolve_factors(MoveArgs& a) {
@@ -730,6 +753,7 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
           nu_n[d * a.cap + dst] = (NT)encode_nu(u, edges, bucket, a.nbucket, a.vhalf);
           chi_n[d * a.cap + dst] = (CT)m.chi[d];
         }
+        if (a.pid_bytes) store_id(a, dst, particle_id<MODE>(a, g, s, (int64_t)start[s] + (i - pre[s]), i - pre[s]));
       } else {
         set_flag(a.flags, FLAG_COUNT);
       }
@@ -1042,6 +1066,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
               nu_n[d * a.cap + dst] = (NT)encode_nu(u, edges, bucket, a.nbucket, a.vhalf);
               chi_n[d * a.cap + dst] = (CT)cq[d];
             }
+            if (a.pid_bytes) store_id(a, dst, particle_id<0>(a, g, s, (int64_t)(base + j), 0u));
           } else {
             set_flag(a.flags, FLAG_COUNT);
           }
@@ -1282,7 +1307,7 @@ template <int NCHI, int NNU>
 __global__ void k_load_encode(const uint32_t* key_sorted, const uint32_t* idx_sorted, const uint16_t* chi_tmp,
                               const float* v_tmp, int64_t n, void* chi_out, void* nu_out, int64_t cap,
                               const float* vc, const float* vinv, int64_t nc3, const float* edges,
-                              const int16_t* bucket, int nbucket, int vhalf) {
+                              const int16_t* bucket, int nbucket, int vhalf, void* pid_out, int pid_bytes) {
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1297,6 +1322,17 @@ __global__ void k_load_encode(const uint32_t* key_sorted, const uint32_t* idx_so
     const float u = (v_tmp[d * n + src] - vc[d * nc3 + c]) * inv;
     no[d * cap + j] = (NT)encode_nu(u, edges, bucket, nbucket, vhalf);
   }
+  // the ID of a loaded particle is its index in the input
+  if (pid_bytes == 8) static_cast<uint64_t*>(pid_out)[j] = (uint64_t)src;
+  else if (pid_bytes == 4) static_cast<uint32_t*>(pid_out)[j] = (uint32_t)src;
+}
+
+// IDs 0 .. n-1 in storage order
+__global__ void k_pid_iota(void* pid, int pid_bytes, int64_t n) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (pid_bytes == 8) static_cast<uint64_t*>(pid)[j] = (uint64_t)j;
+  else static_cast<uint32_t*>(pid)[j] = (uint32_t)j;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1454,6 +1490,9 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   a.flags = s.flags;
   a.kd = dev_sched ? s.sched_dev : nullptr;
   a.kstep = dev_sched ? s.step_dev : nullptr;
+  a.pid = s.pid[s.cur];
+  a.pid_n = s.pid[nxt];
+  a.pid_bytes = s.pid_bytes;
   if (mode == 2) {
     a.psi0 = psi[0];
     a.psi1 = psi[1];
@@ -1537,7 +1576,8 @@ void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, h
 #define CUBE_ENC(X, V)                                                                                       \
   k_load_encode<X, V><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(key2, idx2, chi_tmp, v_tmp, n, s.chi[nxt], \
                                                                    s.nu[nxt], s.capacity, s.vc[nxt], s.vinv, \
-                                                                   s.nc3, s.tedge, s.tbucket, s.nbucket, (s.vm - 1) / 2)
+                                                                   s.nc3, s.tedge, s.tbucket, s.nbucket, (s.vm - 1) / 2, \
+                                                                   s.pid[nxt], s.pid_bytes)
   if (n > 0) {
     CUBE_XV_DISPATCH(s.nchi, s.nnu, CUBE_ENC);
     CUBE_HIP(hipGetLastError());
@@ -1549,6 +1589,12 @@ void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, h
   s.dfree(chi_tmp);
   s.dfree(key);
   s.cur = nxt;
+}
+
+void launch_pid_iota(Sim& s, hipStream_t st) {
+  if (!s.pid_bytes || s.n == 0) return;
+  k_pid_iota<<<(unsigned)((s.n + 255) / 256), 256, 0, st>>>(s.pid[s.cur], s.pid_bytes, s.n);
+  CUBE_HIP(hipGetLastError());
 }
 
 void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st) {
