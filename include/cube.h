@@ -161,6 +161,18 @@ int cube_get_state(cube_sim* sim, cube_state_view* out);
 int cube_get_counts(cube_sim* sim, uint32_t* cnt);
 int cube_set_state(cube_sim* sim, const cube_state_view* in);
 
+/* The coarse-cell counts in the 1-byte checkpoint form of Sec. 2.1: rho1[c] = min(count, 255)
+ * for the nc^3 cells (host, x fastest); every cell marked 255 holds 255 or more particles and
+ * its true count is written to `overflow` (host, 4-byte integers, in cell order). *n_overflow
+ * receives the number of such cells; when it exceeds max_overflow nothing is written to
+ * `overflow` and CUBE_E_CAPACITY is returned (call again with a larger list). */
+int cube_get_counts_u8(cube_sim* sim, uint8_t* rho1, uint32_t* overflow, int64_t max_overflow,
+                       int64_t* n_overflow);
+/* Host-only inverse (no simulation, no GPU): the ncells counts from rho1 and the overflow list.
+ * CUBE_E_INVALID when the list does not match the cells marked 255. */
+int cube_counts_from_u8(const uint8_t* rho1, int64_t ncells, const uint32_t* overflow, int64_t n_overflow,
+                        uint32_t* cnt);
+
 /* Particle IDs, the optional I_P array of Sec. 2.1: one pid_bytes-byte unsigned integer per
  * particle (4 or 8; 0 frees them), stored in the same order as chi and nu and carried through
  * every step, half drift and re-sort. IDs are assigned as follows: cube_init_ic gives each particle

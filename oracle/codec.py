@@ -15,7 +15,9 @@ Conventions (readings of the paper, each listed in the design notes):
 Pins (tests/test_oracle_codec.py): the worked 1-D example printed under Eq. (x);
 encode(decode(chi)) = chi for every code; |x - decode(encode(x))| <= 2^{-8 n_chi - 1};
 encode(decode(nu)) = nu for every velocity code; odd symmetry; the Cauchy/Gaussian peak match
-at nu = 0 stated after Eq. (v).
+at nu = 0 stated after Eq. (v); the 1-byte count export (Sec. 2.1: 255 marks a cell whose
+true count, 255 or more, goes to a separate list of 4-byte integers) round-trips and puts every
+count below 255 in its byte.
 """
 from __future__ import annotations
 
@@ -82,6 +84,25 @@ def cell_order(cid, n_cells: int):
     counts = np.bincount(cid, minlength=n_cells)
     order = np.argsort(cid, kind="stable")
     return counts, order
+
+
+def counts_to_u8(counts):
+    """1-byte coarse density of Sec. 2.1: min(count, 255) per cell, and the true counts of the
+    cells marked 255, in cell order, as 4-byte integers."""
+    c = np.asarray(counts, dtype=np.int64)
+    rho1 = np.minimum(c, 255).astype(np.uint8)
+    overflow = c[c >= 255].astype(np.uint32)
+    return rho1, overflow
+
+
+def counts_from_u8(rho1, overflow):
+    """Inverse of counts_to_u8."""
+    c = np.asarray(rho1, dtype=np.uint8).astype(np.uint32)
+    mark = np.nonzero(c == 255)[0]
+    if len(mark) != len(overflow):
+        raise ValueError("overflow list does not match the cells marked 255")
+    c[mark] = np.asarray(overflow, dtype=np.uint32)
+    return c
 
 
 def cauchy_peak_density(sigma: float) -> float:

@@ -6,7 +6,7 @@ package holds its sources (csrc/), the in-tree build (build.py) and the ctypes b
 when the library has not been built.
 """
 from .binding import (CUBE_DONE, CUBE_OK, EXPORTED, LIB_PATH, SIGMA_GLOBAL, SIGMA_PER_CELL, Batch, CubeError, Server,
-                      Sim, footprint, load_library, make_params)
+                      Sim, counts_from_u8, footprint, load_library, make_params)
 
-__all__ = ["Sim", "Batch", "Server", "CubeError", "footprint", "load_library", "make_params", "LIB_PATH", "EXPORTED",
+__all__ = ["Sim", "Batch", "Server", "CubeError", "counts_from_u8", "footprint", "load_library", "make_params", "LIB_PATH", "EXPORTED",
            "SIGMA_GLOBAL", "SIGMA_PER_CELL", "CUBE_OK", "CUBE_DONE"]

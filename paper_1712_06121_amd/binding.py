@@ -33,6 +33,7 @@ EXPORTED = [
     "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
+    "cube_get_counts_u8", "cube_counts_from_u8",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -121,6 +122,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
     lib.cube_get_cross_power.argtypes = [sim_p, sim_p, c_int32] + [c_void_p] * 5
     lib.cube_enable_pids.argtypes = [sim_p, c_int32]
+    lib.cube_get_counts_u8.argtypes = [sim_p, c_void_p, c_void_p, c_int64, c_void_p]
+    lib.cube_counts_from_u8.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p]
     lib.cube_get_pids.argtypes = [sim_p, c_void_p]
     lib.cube_set_pids.argtypes = [sim_p, c_void_p]
     lib.cube_get_state.argtypes = [sim_p, POINTER(CubeStateView)]
@@ -359,6 +362,18 @@ class Sim:
         self._check(self._lib.cube_get_counts(self._h, _ptr(out)))
         return out
 
+    def get_counts_u8(self):
+        """(rho1 uint8[nc^3], overflow uint32[...]): the 1-byte count export of Sec. 2.1."""
+        rho1 = np.empty(self.nc**3, np.uint8)
+        nov = np.zeros(1, np.int64)
+        over = np.empty(1024, np.uint32)
+        rc = self._lib.cube_get_counts_u8(self._h, _ptr(rho1), _ptr(over), len(over), _ptr(nov))
+        if rc == -4:  # CUBE_E_CAPACITY: the overflow list is longer
+            over = np.empty(int(nov[0]), np.uint32)
+            rc = self._lib.cube_get_counts_u8(self._h, _ptr(rho1), _ptr(over), len(over), _ptr(nov))
+        self._check(rc)
+        return rho1, over[: int(nov[0])].copy()
+
     def set_state(self, cnt, chi, nu, vc, vs, steps_done: int = 0):
         cnt = np.ascontiguousarray(cnt, np.uint32)
         chi = np.ascontiguousarray(chi, self.chi_dtype)
@@ -502,6 +517,18 @@ class Batch:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def counts_from_u8(rho1, overflow) -> np.ndarray:
+    """Counts from the 1-byte export (host only, no GPU)."""
+    lib = load_library()
+    rho1 = np.ascontiguousarray(rho1, np.uint8)
+    overflow = np.ascontiguousarray(overflow, np.uint32)
+    out = np.empty(len(rho1), np.uint32)
+    rc = lib.cube_counts_from_u8(_ptr(rho1), len(rho1), _ptr(overflow), len(overflow), _ptr(out))
+    if rc != CUBE_OK:
+        raise CubeError(rc, "overflow list does not match the cells marked 255")
+    return out
 
 
 def footprint(**cfg) -> int:

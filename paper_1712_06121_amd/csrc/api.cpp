@@ -626,6 +626,48 @@ int cube_get_counts(cube_sim* sim, uint32_t* cnt) {
   return CUBE_OK;
 }
 
+int cube_get_counts_u8(cube_sim* sim, uint8_t* rho1, uint32_t* overflow, int64_t max_overflow, int64_t* n_overflow) {
+  if (!sim || !rho1 || !n_overflow || max_overflow < 0 || (max_overflow > 0 && !overflow)) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  CUBE_GUARD(sim, {
+    uint8_t* d1 = static_cast<uint8_t*>(s.dmalloc((size_t)s.nc3));
+    uint32_t* dov = static_cast<uint32_t*>(s.dmalloc(sizeof(uint32_t) * (size_t)s.nc3));
+    int64_t n = 0;
+    try {
+      n = cube::launch_counts_u8(s, d1, dov, s.stream);
+      CUBE_HIP(hipMemcpyAsync(rho1, d1, (size_t)s.nc3, hipMemcpyDeviceToHost, s.stream));
+      if (n <= max_overflow && n > 0)
+        CUBE_HIP(hipMemcpyAsync(overflow, dov, sizeof(uint32_t) * (size_t)n, hipMemcpyDeviceToHost, s.stream));
+      CUBE_HIP(hipStreamSynchronize(s.stream));
+    } catch (...) {
+      s.dfree(dov);
+      s.dfree(d1);
+      throw;
+    }
+    s.dfree(dov);
+    s.dfree(d1);
+    *n_overflow = n;
+    if (n > max_overflow) throw Error{CUBE_E_CAPACITY, "more cells hold 255 or more particles than max_overflow"};
+  });
+  return CUBE_OK;
+}
+
+int cube_counts_from_u8(const uint8_t* rho1, int64_t ncells, const uint32_t* overflow, int64_t n_overflow,
+                        uint32_t* cnt) {
+  if (!rho1 || !cnt || ncells < 0 || n_overflow < 0 || (n_overflow > 0 && !overflow)) return CUBE_E_INVALID;
+  int64_t j = 0;
+  for (int64_t c = 0; c < ncells; ++c) {
+    if (rho1[c] < 255) {
+      cnt[c] = rho1[c];
+    } else {
+      if (j >= n_overflow) return CUBE_E_INVALID;
+      if (overflow[j] < 255) return CUBE_E_INVALID;
+      cnt[c] = overflow[j++];
+    }
+  }
+  return j == n_overflow ? CUBE_OK : CUBE_E_INVALID;
+}
+
 int cube_get_state(cube_sim* sim, cube_state_view* out) {
   if (!sim || !out || !out->cnt || !out->chi || !out->nu || !out->vc || !out->vs) return CUBE_E_INVALID;
   cube::Sim& s = sim->s;

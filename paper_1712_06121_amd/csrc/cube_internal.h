@@ -174,6 +174,9 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
                  hipEvent_t* evs, bool dev_sched = false);
 void launch_advance_step(Sim& s, hipStream_t st);
 void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream_t st);
+// 1-byte counts into rho1 (nc3 bytes, device) and the counts >= 255 in cell order into over
+// (nc3 entries at most, device); returns the number of the latter
+int64_t launch_counts_u8(Sim& s, uint8_t* rho1, uint32_t* over, hipStream_t st);
 // particle IDs 0 .. n-1 in storage order (when IDs are enabled)
 void launch_pid_iota(Sim& s, hipStream_t st);
 void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmodes);

@@ -1597,6 +1597,36 @@ void launch_pid_iota(Sim& s, hipStream_t st) {
   CUBE_HIP(hipGetLastError());
 }
 
+// 1-byte coarse density (Sec. 2.1): min(count, 255) per cell
+__global__ void k_counts_u8(const uint32_t* cnt, int64_t nc3, uint8_t* rho1) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc3) return;
+  const uint32_t v = cnt[c];
+  rho1[c] = (uint8_t)(v < 255u ? v : 255u);
+}
+
+struct AtLeast255 {
+  __device__ bool operator()(uint32_t v) const { return v >= 255u; }
+};
+
+int64_t launch_counts_u8(Sim& s, uint8_t* rho1, uint32_t* over, hipStream_t st) {
+  const uint32_t* cnt = s.cnt[s.cur];
+  k_counts_u8<<<(unsigned)((s.nc3 + 255) / 256), 256, 0, st>>>(cnt, s.nc3, rho1);
+  CUBE_HIP(hipGetLastError());
+  // the true counts of the cells marked 255, in cell order (a stable selection)
+  size_t* nsel = static_cast<size_t*>(s.dmalloc(sizeof(size_t)));
+  size_t tmp_bytes = 0;
+  CUBE_HIP(rocprim::select(nullptr, tmp_bytes, cnt, over, nsel, (size_t)s.nc3, AtLeast255(), st));
+  void* tmp = s.dmalloc(tmp_bytes > 0 ? tmp_bytes : 16);
+  CUBE_HIP(rocprim::select(tmp, tmp_bytes, cnt, over, nsel, (size_t)s.nc3, AtLeast255(), st));
+  size_t n = 0;
+  CUBE_HIP(hipMemcpyAsync(&n, nsel, sizeof(size_t), hipMemcpyDeviceToHost, st));
+  CUBE_HIP(hipStreamSynchronize(st));
+  s.dfree(tmp);
+  s.dfree(nsel);
+  return (int64_t)n;
+}
+
 void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st) {
   const int64_t plane = (int64_t)pl.n * pl.n;
   const dim3 grid((unsigned)((plane + 255) / 256), (unsigned)pl.n);

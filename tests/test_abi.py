@@ -51,3 +51,18 @@ def test_footprint_is_host_arithmetic():
     assert abs(resident / 180.1e9 - 1) < 1e-3
     sizes = [footprint(**dict(c3, np_side=n, nm_side=n, nc_side=n // 4)) for n in (64, 128, 256, 512)]
     assert all(a < b for a, b in zip(sizes, sizes[1:]))
+
+
+def test_counts_from_u8_is_host_only_and_matches_the_oracle():
+    from paper_1712_06121_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("libcube.so not built (run __graft_entry__.build())")
+    import numpy as np
+    from oracle import codec
+    g = np.random.default_rng(5)
+    counts = g.integers(0, 300, size=4096).astype(np.uint32)
+    counts[[0, 17, 4095]] = [255, 1 << 20, 254]
+    rho1, over = codec.counts_to_u8(counts)
+    assert np.array_equal(binding.counts_from_u8(rho1, over), counts)
+    with pytest.raises(binding.CubeError):
+        binding.counts_from_u8(rho1, over[:-1])

@@ -1,4 +1,5 @@
-"""Particle IDs (the optional I_P array of Sec. 2.1) and the displacement test of Sec. 3
+"""Particle IDs (the optional I_P array of Sec. 2.1), the 1-byte count export of the checkpoint,
+and the displacement test of Sec. 3
 (Eq. (offset)): IDs follow their particles through the initial conditions, the load path, every
 step and the re-sort, change nothing else in the state, and let the final positions be compared
 particle by particle with the FP64 oracle's uncompressed run from the same initial conditions."""
@@ -189,3 +190,24 @@ def test_displacement_offsets_against_oracle(lib):
     # measured medians (fine cells): x2v2 0.0005, x2v1 0.024, x1v2 0.192, x1v1 0.195; |Psi| 3.4
     assert med["x2v2"] < med["x2v1"] < min(med["x1v2"], med["x1v1"])
     assert med["x1v1"] < 0.1 * np.median(absd)
+
+
+def test_one_byte_count_export_with_overflow_cells(lib):
+    """The checkpoint's 1-byte rho_c (Sec. 2.1) with cells of 255 or more particles."""
+    from oracle import codec
+    cfg = dict(synth.WORKLOADS["c1_pm32"], capacity=40000)
+    nm = cfg["nm_side"]
+    g = np.random.default_rng(23)
+    q = displacement.lattice_positions(cfg["np_side"], nm)
+    crowd = [np.array([1.0, 1.0, 1.0]) + g.uniform(0, 2, size=(600, 3)),   # inside coarse cell (0, 0, 0)
+             np.array([21.0, 9.0, 45.0]) + g.uniform(0, 2, size=(255, 3)),  # exactly 255 extra
+             np.array([41.0, 61.0, 5.0]) + g.uniform(0, 2, size=(246, 3))]  # 8 + 246 = 254: no overflow
+    x = np.concatenate([q] + crowd)
+    with lib.Sim(**cfg) as sim:
+        sim.load_particles(x, np.zeros_like(x))
+        cnt = sim.get_counts()
+        rho1, over = sim.get_counts_u8()
+    r0, o0 = codec.counts_to_u8(cnt)
+    assert np.array_equal(rho1, r0) and np.array_equal(over, o0)
+    assert over.tolist() == [608, 263]  # cell order: cell 0, then cell 5 + 16 (2 + 16 * 11)
+    assert np.array_equal(lib.counts_from_u8(rho1, over), cnt)

@@ -206,7 +206,7 @@ def _full_run_power(Sim, name, nbins=None):
         return sim.get_power(nbins)
 
 
-@pytest.mark.parametrize("name", ["c1_pm32", "c2_pm128"])
+@pytest.mark.parametrize("name", ["c1_pm32", "c2_pm128", "c3_sibling256"])
 def test_full_run_power_within_one_percent(Sim, name):
     """P(k) at a = 1 from identical ICs, GPU (compressed, FP32) vs oracle (uncompressed, FP64),
     k_Nyquist = pi N_m / L. 2-byte positions and velocities: within 1% for every shell below

@@ -72,3 +72,13 @@ def test_cell_order_is_stable():
     counts, order = codec.cell_order(cid, 4)
     assert list(counts) == [2, 1, 3, 0]
     assert list(order) == [1, 4, 3, 0, 2, 5]
+
+
+def test_one_byte_count_export():
+    counts = np.array([0, 3, 254, 255, 256, 7, 1000, 12], dtype=np.uint32)
+    rho1, over = codec.counts_to_u8(counts)
+    assert rho1.tolist() == [0, 3, 254, 255, 255, 7, 255, 12]
+    assert over.dtype == np.uint32 and over.tolist() == [255, 256, 1000]  # cell order
+    assert np.array_equal(codec.counts_from_u8(rho1, over), counts)
+    with pytest.raises(ValueError):
+        codec.counts_from_u8(rho1, over[:2])
