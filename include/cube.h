@@ -98,6 +98,15 @@ const char* cube_last_error(const cube_sim* sim);
  * np_side^3 lattice, FFT, BBKS amplitude, spectral displacement with Nyquist planes removed,
  * then the two particle passes (count, then encode in cell order). Resets the schedule. */
 int cube_init_ic(cube_sim* sim);
+/* Refined initial conditions, for the PM-error reference of Sec. 3 (the same initial conditions
+ * with more particles and cells): with parent_np > 0 every later cube_init_ic and
+ * cube_get_ic_displacement takes, for each mode with all |n_i| < parent_np/2, the transformed
+ * white noise of the parent_np^3 lattice of the same seed, scaled by (np_side/parent_np)^{3/2},
+ * so a run of this simulation and one of np_side = parent_np hold the same Gaussian field on
+ * those scales; every other mode comes from this lattice's own noise, drawn with the seed XOR
+ * 0x9E3779B97F4A7C15. parent_np must divide np_side, be smaller and be a supported FFT size;
+ * 0 switches refinement off. Errors: CUBE_E_INVALID. */
+int cube_set_ic_parent(cube_sim* sim, int32_t parent_np);
 
 /* Replace the particles by n host particles: x (n,3) positions in fine cells, v (n,3) momenta,
  * both FP64 row-major. Positions are encoded with Eq. (chi) in FP64, velocities rounded to

@@ -14,6 +14,13 @@ Steps, in the paper's order:
 4. Lattice point q = (i + 1/2) L / N_p; x = q + Psi; momentum p = a^2 E(a) f(a) Psi at a_i
    (growing mode: dx/dt = H f Psi).
 
+Refined initial conditions (the PM-error reference of Sec. 3: the same initial conditions with
+8 times more particles and cells): the noise of an N_p^3 run refined from an N_q^3 parent
+(N_q divides N_p) takes, for every mode with all |n_i| < N_q/2, the parent's transformed noise
+scaled by (N_p/N_q)^{3/2} (so both runs hold one Gaussian field on those scales); the other modes
+come from the run's own noise, drawn with seed XOR REFINE_KEY. Reading: the paper does not say
+how its higher-resolution run shares the initial conditions.
+
 Output is in fine-mesh units (lengths in cells of the N_m mesh, H0 = 1), particles in
 lattice order. Pins: tests/test_oracle_ic.py (a single-mode field reproduces the analytic
 displacement; the measured P(k) of the IC density tracks the input spectrum).
@@ -49,6 +56,22 @@ def displacement_field(noise, box: float, cosmo: Cosmology, a: float):
     with np.errstate(divide="ignore", invalid="ignore"):
         phik = np.where(k2 > 0, dk / k2, 0.0)
     return [np.fft.irfftn(1j * kd * phik, s=noise.shape, axes=(0, 1, 2)) for kd in (kx, ky, kz)]
+
+
+REFINE_KEY = 0x9E3779B97F4A7C15
+
+
+def refined_noise(seed: int, n: int, parent_n: int):
+    """White noise on the n^3 lattice whose modes with every |n_i| < parent_n/2 are the parent's
+    (n^3 lattice noise of seed ^ REFINE_KEY elsewhere), as a real array [z, y, x]."""
+    own = np.fft.rfftn(white_noise_grid(seed ^ REFINE_KEY, n))
+    par = np.fft.rfftn(white_noise_grid(seed, parent_n))
+    f = np.rint(np.fft.fftfreq(parent_n) * parent_n).astype(np.int64)
+    keep = np.abs(f) < parent_n // 2
+    fl = f[keep]
+    fx = np.arange(parent_n // 2)
+    own[np.ix_(fl % n, fl % n, fx)] = par[np.ix_(fl % parent_n, fl % parent_n, fx)] * (n / parent_n) ** 1.5
+    return np.fft.irfftn(own, s=(n, n, n), axes=(0, 1, 2))
 
 
 def zeldovich(np_side: int, nm_side: int, box: float, cosmo: Cosmology, a: float, seed: int,

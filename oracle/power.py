@@ -63,7 +63,8 @@ def power_spectrum(delta, box: float):
 
 
 def _signed(nm):
-    return np.fft.fftfreq(nm) * nm
+    """Signed integer frequency of each index (fftfreq times nm is not exact for every size)."""
+    return np.rint(np.fft.fftfreq(nm) * nm).astype(np.int64)
 
 
 def cross_spectrum(delta_a, delta_b, box: float):
@@ -86,7 +87,7 @@ def cross_spectrum(delta_a, delta_b, box: float):
             (fx[None, None, :] < n / 2)
 
         def take(f, m):
-            iz = (fz.astype(np.int64) % m)
+            iz = fz % m
             return f[np.ix_(iz, iz, fx)]
 
         ca, cb = take(fa, na), take(fb, nb_)

@@ -33,7 +33,7 @@ EXPORTED = [
     "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
-    "cube_get_counts_u8", "cube_counts_from_u8",
+    "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
     lib.cube_get_cross_power.argtypes = [sim_p, sim_p, c_int32] + [c_void_p] * 5
     lib.cube_enable_pids.argtypes = [sim_p, c_int32]
+    lib.cube_set_ic_parent.argtypes = [sim_p, c_int32]
     lib.cube_get_counts_u8.argtypes = [sim_p, c_void_p, c_void_p, c_int64, c_void_p]
     lib.cube_counts_from_u8.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p]
     lib.cube_get_pids.argtypes = [sim_p, c_void_p]
@@ -320,6 +321,10 @@ class Sim:
         k, pk, nm = (np.empty(nb) for _ in range(3))
         self._check(self._lib.cube_get_power(self._h, nb, _ptr(k), _ptr(pk), _ptr(nm)))
         return k, pk, nm
+
+    def set_ic_parent(self, parent_np: int):
+        """Refine the initial conditions from a parent_np^3 lattice of the same seed (0: off)."""
+        self._check(self._lib.cube_set_ic_parent(self._h, parent_np))
 
     def enable_pids(self, pid_bytes: int = 8):
         """Carry a particle ID of pid_bytes (4 or 8; 0 drops them) through every step."""

@@ -162,8 +162,29 @@ void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps, b
     psi[d] = static_cast<float*>(s.dmalloc(fbytes));
     temps.push_back(psi[d]);
   }
-  launch_noise(s.lat_plan, wk, s.p.seed, s.stream);
+  // refined from a parent lattice: own noise from a second stream, the parent's on its scales
+  const uint64_t refine_key = 0x9E3779B97F4A7C15ull;
+  launch_noise(s.lat_plan, wk, s.ic_parent_np ? (s.p.seed ^ refine_key) : s.p.seed, s.stream);
   fft_forward_3d(s.lat_plan, wk, s.stream);
+  if (s.ic_parent_np) {
+    FFTPlan pp;
+    fft_plan_create(s, pp, s.ic_parent_np);
+    float* pw = nullptr;
+    try {
+      pw = static_cast<float*>(s.dmalloc(pp.field_floats() * sizeof(float)));
+      launch_noise(pp, pw, s.p.seed, s.stream);
+      fft_forward_3d(pp, pw, s.stream);
+      splice_modes(pp, pw, s.lat_plan, wk, (float)std::pow((double)s.np / (double)s.ic_parent_np, 1.5), s.stream);
+      CUBE_HIP(hipStreamSynchronize(s.stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(s.stream);
+      if (pw) s.dfree(pw);
+      fft_plan_destroy(s, pp);
+      throw;
+    }
+    s.dfree(pw);
+    fft_plan_destroy(s, pp);
+  }
   // i n_d tab[|n|^2] gives the displacement in fine cells after the unnormalised inverse FFT
   const int h = s.np / 2;
   const int64_t ntab = 3LL * h * h + 1;
@@ -407,6 +428,17 @@ int cube_init_ic(cube_sim* sim) {
     cube::reset_schedule(s);
     cube::check_flags(s);
   });
+  return CUBE_OK;
+}
+
+int cube_set_ic_parent(cube_sim* sim, int32_t parent_np) {
+  if (!sim) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  if (parent_np != 0 && (parent_np < 2 || parent_np >= s.np || s.np % parent_np != 0 ||
+                         !cube::fft_size_supported(parent_np)))
+    return cube::fail(sim, Error{CUBE_E_INVALID,
+                                 "parent_np must be 0 or a supported FFT size that divides np_side and is smaller"});
+  s.ic_parent_np = parent_np;
   return CUBE_OK;
 }
 

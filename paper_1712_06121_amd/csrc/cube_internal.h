@@ -112,6 +112,7 @@ struct Sim {
   int nbucket = 0;
   std::vector<float> h_tdec, h_tedge;
   int vm = 255;
+  int ic_parent_np = 0;  // initial conditions refined from an ic_parent_np^3 parent (0: none)
 
   // power spectrum accumulators
   double* pk_acc = nullptr;  // 5 x (nm/2 + 1): auto (3 rows) or cross (5 rows) shell sums
@@ -159,6 +160,9 @@ void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st);
 // evs (optional): 6 events recorded before the first pass and after each of the five passes
 void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs = nullptr);
 void fft_power(const FFTPlan& pl, float* data, double* acc, hipStream_t st);
+// the modes with every |n_i| < np/2 of the forward-transformed field src (plan ps, size np) into
+// dst (plan pd, a larger size), scaled
+void splice_modes(const FFTPlan& ps, const float* src, const FFTPlan& pd, float* dst, float scale, hipStream_t st);
 // shell sums of two forward-transformed meshes over one box: 5 x (n/2 + 1) doubles, n the smaller size
 void cross_shells(const FFTPlan& pa, const float* a, const FFTPlan& pb, const float* b, double* acc,
                   hipStream_t st);

@@ -627,6 +627,32 @@ void cross_shells(const FFTPlan& pa, const float* a, const FFTPlan& pb, const fl
   CUBE_HIP(hipGetLastError());
 }
 
+// Refined initial conditions: the modes a coarser lattice holds without aliasing (every
+// |n_i| < np/2 of the source, size np) overwrite the same modes of the finer lattice's transformed
+// noise, times (N/np)^{3/2} so that both hold one Gaussian field. One thread per source mode.
+__global__ void k_splice_modes(const float2* __restrict__ src, int64_t ps, int ns, float2* __restrict__ dst,
+                               int64_t pd, int nd, float scale) {
+  const int half = ns / 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)ns * ns * half;
+  if (i >= total) return;
+  const int fx = (int)(i % half);
+  const int iy = (int)((i / half) % ns), iz = (int)(i / ((int64_t)half * ns));
+  const int fy = signed_freq(iy, ns), fz = signed_freq(iz, ns);
+  if (fy == half || fz == half) return;  // the source's Nyquist planes are aliased
+  const int yd = fy < 0 ? fy + nd : fy, zd = fz < 0 ? fz + nd : fz;
+  const float2 v = src[((int64_t)iz * ns + iy) * ps + fx];
+  dst[((int64_t)zd * nd + yd) * pd + fx] = make_float2(v.x * scale, v.y * scale);
+}
+
+void splice_modes(const FFTPlan& ps, const float* src, const FFTPlan& pd, float* dst, float scale, hipStream_t st) {
+  const int64_t total = (int64_t)ps.n * ps.n * (ps.n / 2);
+  k_splice_modes<<<(unsigned)((total + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float2*>(src), ps.pitch_c,
+                                                                   ps.n, reinterpret_cast<float2*>(dst), pd.pitch_c,
+                                                                   pd.n, scale);
+  CUBE_HIP(hipGetLastError());
+}
+
 bool fft_size_supported(int n) {
   switch (n) {
     case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 1024: case 2048:

@@ -45,6 +45,53 @@ def test_ic_displacement_matches_oracle(Sim, name, np_side, nm):
     assert err < 1e-5, err
 
 
+@pytest.mark.parametrize("np_side,parent", [(64, 32), (96, 48), (128, 32)])
+def test_refined_ic_displacement_matches_oracle(Sim, np_side, parent):
+    cfg = dict(synth.WORKLOADS["c1_pm32"], np_side=np_side, nm_side=2 * np_side, nc_side=np_side // 2)
+    nm = cfg["nm_side"]
+    with Sim(**cfg) as sim:
+        sim.set_ic_parent(parent)
+        got = sim.get_ic_displacement()
+    cosmo = cosmo_of(cfg)
+    noise = ic.refined_noise(cfg["seed"], np_side, parent)
+    ref = np.stack(ic.displacement_field(noise, cfg["box"], cosmo, cfg["a_init"])) * (nm / cfg["box"])
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-5, err
+
+
+def test_refined_ic_validation(Sim):
+    with Sim(**synth.WORKLOADS["c1_pm32"]) as sim:
+        for bad in (32, 64, 12, 20, 1):
+            with pytest.raises(Exception):
+                sim.set_ic_parent(bad)
+        sim.set_ic_parent(0)
+
+
+def test_pm_error_reference_and_compression_decorrelation(Sim):
+    """Fig. ccc's comparison: the decorrelation that x1v1 causes against x2v2, and the PM
+    decorrelation, measured by cross-correlating x2v2 with an x2v2 run from the same initial
+    conditions at 8 times the particles and cells (refined ICs). The paper finds the former no
+    worse than the latter."""
+    base = dict(synth.WORKLOADS["c1_pm32"], x_bytes=2, v_bytes=2)
+    fine = dict(base, np_side=64, nm_side=128, nc_side=32)
+    with Sim(**base) as a, Sim(**dict(base, x_bytes=1, v_bytes=1)) as b, Sim(**fine) as c:
+        c.set_ic_parent(base["np_side"])
+        for s in (a, b, c):
+            s.init_ic()
+            s.step(base["n_steps"])
+        k, paa, pbb, pab, _ = a.get_cross_power(b)
+        xi_codec = power.correlation(paa, pbb, pab)
+        k2, pa2, pc2, pac, _ = a.get_cross_power(c)
+        xi_pm = power.correlation(pa2, pc2, pac)
+    kny = np.pi * base["nm_side"] / base["box"]
+    sel = k < kny / 2
+    assert np.allclose(k[sel], k2[sel])  # the top shell differs: no Nyquist-plane modes across sizes
+    print("1 - xi, x1v1 vs x2v2:", np.round(1 - xi_codec[sel], 5))
+    print("1 - xi, PM (x2v2 vs 8x x2v2):", np.round(1 - xi_pm[sel], 5))
+    assert np.all(xi_pm[:2] > 0.99)  # one Gaussian field on the largest scales
+    assert np.all(1 - xi_codec[sel] <= 1 - xi_pm[sel])
+
+
 def test_ic_state_matches_oracle_ic(Sim):
     cfg = synth.WORKLOADS["c1_pm32"]
     nc, nm = cfg["nc_side"], cfg["nm_side"]

@@ -80,30 +80,34 @@ def test_cross_of_independent_noise_is_zero_within_scatter():
     assert np.all(np.abs(xi[sel]) < 5 / np.sqrt(nmodes[sel]))
 
 
-def test_cross_between_mesh_sizes_uses_the_common_modes():
+@pytest.mark.parametrize("small", [16, 24])
+def test_cross_between_mesh_sizes_uses_the_common_modes(small):
     box, amp = 70.0, 0.1
     waves = [(3, -5, 2), (-1, 4, 6), (7, 0, -3)]  # (n_x, n_y, n_z), every |n_i| < 8
+    if small == 24:
+        waves += [(-10, 3, -5), (11, -2, 1)]  # |n_i| up to 11 < 12, shells 12 and 11
 
     def field(nm):
         z, y, x = _grid(nm)
         return sum(amp * np.cos(2 * np.pi * (nx * x + ny * y + nz * z) / nm + 0.4 * j)
                    for j, (nx, ny, nz) in enumerate(waves))
 
-    a, b = field(16), field(32)
+    a, b = field(small), field(2 * small)
     k, paa, pbb, pab, nmodes = power.cross_spectrum(a, b, box)
-    assert len(k) == 8
+    assert len(k) == small // 2
     shells = sorted({int(np.floor(np.sqrt(nx * nx + ny * ny + nz * nz) + 0.5)) for nx, ny, nz in waves})
     live = np.nonzero(paa * nmodes > 1e-20)[0] + 1
     assert live.tolist() == shells
     for p in (paa, pbb, pab):  # the same band-limited field on both meshes: one spectrum
         assert (p * nmodes).sum() == pytest.approx(len(waves) * amp**2 / 2 * box**3, rel=1e-10)
     assert np.allclose(power.correlation(paa, pbb, pab)[live - 1], 1.0, rtol=1e-10)
-    # the mode counts: integer vectors with every |n_i| < 8, shell floor(|n| + 1/2), brute force
-    f = np.arange(-7, 8)
+    # the mode counts: integer vectors with every |n_i| < small/2, shell floor(|n| + 1/2), brute force
+    h = small // 2
+    f = np.arange(-h + 1, h)
     n2 = f[:, None, None] ** 2 + f[None, :, None] ** 2 + f[None, None, :] ** 2
     sh = np.floor(np.sqrt(n2) + 0.5)
-    assert np.array_equal(nmodes, [(sh == s).sum() for s in range(1, 9)])
+    assert np.array_equal(nmodes, [(sh == s).sum() for s in range(1, h + 1)])
     # a scaled copy on the same mesh size keeps xi = 1 and scales P_ab linearly
-    _, _, _, pab2, _ = power.cross_spectrum(field(16), 3.0 * field(16), box)
-    _, p16, _, _, _ = power.cross_spectrum(field(16), field(16), box)
+    _, _, _, pab2, _ = power.cross_spectrum(field(small), 3.0 * field(small), box)
+    _, p16, _, _, _ = power.cross_spectrum(field(small), field(small), box)
     assert np.allclose(pab2, 3.0 * p16, rtol=1e-12)
