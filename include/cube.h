@@ -120,6 +120,28 @@ int cube_load_particles(cube_sim* sim, const double* x, const double* v, int64_t
  * Errors: CUBE_E_CFL, CUBE_E_NONFINITE, CUBE_E_OVERFLOW, CUBE_E_STATE. */
 int cube_step(cube_sim* sim, int32_t k);
 
+/* Adaptive time steps (Sec. 2.3.3: the step is bounded by the particles' largest velocity and
+ * acceleration and by the expansion), chosen before the first step; eta_v = eta_a = eta_e = 0
+ * returns to the fixed schedule. Each interval [a0, a1] of the kicks is the largest with
+ * a1 <= a0 (1 + eta_e), a1 <= a_final, vmax Delta(a0, a1) <= eta_v and
+ * gmax K(a0, a1) Delta(a0, a1) <= eta_a (fine cells; Delta and K the drift and kick factors,
+ * vmax the largest speed and gmax the largest force per unit kick factor), found by bisection.
+ * The maxima come from the step two intervals earlier (the first two intervals: the largest speed
+ * of the state and no force), because a step's drift already ends at the middle of the next
+ * interval. n_steps bounds the number of steps (CUBE_E_STATE beyond it); cube_step returns
+ * CUBE_DONE once a_final is reached. Every step reads the maxima back (one synchronisation).
+ * Not for batches. Errors: CUBE_E_INVALID, CUBE_E_STATE (after the first step), CUBE_E_CFL
+ * (a step that would shrink to nothing). */
+int cube_set_adaptive(cube_sim* sim, double eta_v, double eta_a, double eta_e);
+/* The adaptive schedule so far: the interval ends a_int[0 .. *n_a - 1] (a_int[0] = a_init) and
+ * the maxima vmax, gmax[0 .. *n_meas - 1] (index 0: the state before the first step; j + 1: step
+ * j). At most max_entries of each are written. CUBE_E_STATE when adaptive steps are off. */
+int cube_get_adaptive_log(cube_sim* sim, int32_t max_entries, double* a_int, double* vmax, double* gmax,
+                          int32_t* n_a, int32_t* n_meas);
+/* The largest speed and force per unit kick factor of the last step pass (also after
+ * cube_stage_move), when adaptive steps are on; CUBE_E_STATE otherwise. */
+int cube_get_last_maxima(cube_sim* sim, double* vmax, double* gmax);
+
 /* Scale factor of the particle positions (a_init before the first step, a_final at the end). */
 double cube_scale_factor(const cube_sim* sim);
 /* Number of steps completed. */

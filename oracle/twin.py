@@ -304,6 +304,7 @@ def move(st: State, phi32: np.ndarray, kfac32, dfac32, sigma_mode: int = SIGMA_P
         return F32(8) * a - b
 
     vnew = np.empty_like(v)
+    tgrad = np.empty_like(v)
     for d in range(3):
         s = []
         for cz in (0, 1):
@@ -314,6 +315,7 @@ def move(st: State, phi32: np.ndarray, kfac32, dfac32, sigma_mode: int = SIGMA_P
                 r.append(w[0][0] * d0 + w[0][1] * d1)
             s.append(w[1][0] * r[0] + w[1][1] * r[1])
         t = w[2][0] * s[0] + w[2][1] * s[1]
+        tgrad[d] = t
         vnew[d] = v[d] + t * kf
     lnew = l + vnew * df
     cfl = bool(np.any(~np.isfinite(lnew)) or np.any(lnew < F32(-4)) or np.any(lnew >= F32(8)))
@@ -338,5 +340,5 @@ def move(st: State, phi32: np.ndarray, kfac32, dfac32, sigma_mode: int = SIGMA_P
     new = State(nc, st.nchi, st.nnu, n.astype(np.uint32), chi, nu, vc, vs)
     if return_info:
         dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1)
-        return new, dict(cfl=cfl, dcode=dcode, perm=perm, v=vnew, l=lnew)
+        return new, dict(cfl=cfl, dcode=dcode, perm=perm, v=vnew, l=lnew, t=tgrad)
     return new

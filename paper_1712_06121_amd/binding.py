@@ -33,7 +33,8 @@ EXPORTED = [
     "cube_set_variant", "cube_batch_create", "cube_batch_destroy", "cube_batch_last_error", "cube_batch_size",
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
-    "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent",
+    "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent", "cube_set_adaptive",
+    "cube_get_adaptive_log", "cube_get_last_maxima",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -123,6 +124,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_get_cross_power.argtypes = [sim_p, sim_p, c_int32] + [c_void_p] * 5
     lib.cube_enable_pids.argtypes = [sim_p, c_int32]
     lib.cube_set_ic_parent.argtypes = [sim_p, c_int32]
+    lib.cube_set_adaptive.argtypes = [sim_p, c_double, c_double, c_double]
+    lib.cube_get_adaptive_log.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    lib.cube_get_last_maxima.argtypes = [sim_p, c_void_p, c_void_p]
     lib.cube_get_counts_u8.argtypes = [sim_p, c_void_p, c_void_p, c_int64, c_void_p]
     lib.cube_counts_from_u8.argtypes = [c_void_p, c_int64, c_void_p, c_int64, c_void_p]
     lib.cube_get_pids.argtypes = [sim_p, c_void_p]
@@ -321,6 +325,24 @@ class Sim:
         k, pk, nm = (np.empty(nb) for _ in range(3))
         self._check(self._lib.cube_get_power(self._h, nb, _ptr(k), _ptr(pk), _ptr(nm)))
         return k, pk, nm
+
+    def set_adaptive(self, eta_v: float, eta_a: float, eta_e: float):
+        """Adaptive time steps bounded by the largest drift (eta_v fine cells), the drift of the
+        largest velocity change (eta_a fine cells) and the expansion (Delta a / a <= eta_e)."""
+        self._check(self._lib.cube_set_adaptive(self._h, eta_v, eta_a, eta_e))
+
+    def get_adaptive_log(self):
+        """(a_int, vmax, gmax) of the adaptive schedule so far."""
+        m = self.n_steps + 8
+        a, v, g = np.empty(m), np.empty(m), np.empty(m)
+        na, nv = np.zeros(1, np.int32), np.zeros(1, np.int32)
+        self._check(self._lib.cube_get_adaptive_log(self._h, m, _ptr(a), _ptr(v), _ptr(g), _ptr(na), _ptr(nv)))
+        return a[: na[0]].copy(), v[: nv[0]].copy(), g[: nv[0]].copy()
+
+    def get_last_maxima(self):
+        v, g = np.zeros(1), np.zeros(1)
+        self._check(self._lib.cube_get_last_maxima(self._h, _ptr(v), _ptr(g)))
+        return float(v[0]), float(g[0])
 
     def set_ic_parent(self, parent_np: int):
         """Refine the initial conditions from a parent_np^3 lattice of the same seed (0: off)."""

@@ -113,6 +113,85 @@ void build_schedule(Sim& s) {
 void reset_schedule(Sim& s) {
   s.steps_done = 0;
   s.half_drift_done = false;
+  if (s.adaptive) {
+    s.a_int.clear();
+    s.a_half.clear();
+    s.meas_v.clear();
+    s.meas_g.clear();
+    std::fill(s.kicks.begin(), s.kicks.end(), 0.0);
+    std::fill(s.drifts.begin(), s.drifts.end(), 0.0);
+    s.drift0 = 0.0;
+  }
+}
+
+// The end of the next interval from a0 (Sec. 2.3.3: the step is bounded by the particles' largest
+// speed and acceleration and by the expansion): the largest a1 <= min(a0 (1 + eta_e), a_final)
+// with vmax Delta(a0, a1) <= eta_v (the largest drift, fine cells) and
+// gmax K(a0, a1) Delta(a0, a1) <= eta_a (the drift of the largest velocity change), by bisection.
+double adaptive_next(const Sim& s, double a0, double vmax, double gmax) {
+  const double af = s.p.a_final;
+  double hi = std::min(a0 * (1.0 + s.eta_e), af);
+  auto ok = [&](double a1) {
+    const double d = s.cosmo.drift(a0, a1);
+    if (vmax * d > s.eta_v) return false;
+    return gmax * s.cosmo.kick(a0, a1) * d <= s.eta_a;
+  };
+  if (ok(hi)) return hi;
+  double lo = a0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (ok(mid)) lo = mid;
+    else hi = mid;
+  }
+  if (!(lo > a0)) throw Error{CUBE_E_CFL, "the adaptive time step collapsed to zero"};
+  return lo;
+}
+
+void read_maxima(Sim& s, double* vmax, double* gmax) {
+  uint32_t bits[2] = {0u, 0u};
+  CUBE_HIP(hipMemcpyAsync(bits, s.amax, sizeof(bits), hipMemcpyDeviceToHost, s.stream));
+  CUBE_HIP(hipStreamSynchronize(s.stream));
+  float f[2];
+  std::memcpy(f, bits, sizeof(f));
+  *vmax = std::sqrt((double)f[0]);
+  *gmax = std::sqrt((double)f[1]) / 12.0;  // t is 12 times the force per unit kick factor
+}
+
+int enqueue_adaptive(Sim& s, int k) {
+  const double af = s.p.a_final;
+  for (int i = 0; i < k; ++i) {
+    if (!s.half_drift_done) {
+      const double v0 = std::sqrt((double)launch_state_speed2(s, s.stream));
+      s.meas_v.assign(1, v0);
+      s.meas_g.assign(1, 0.0);
+      s.a_int.assign(1, s.p.a_init);
+      s.a_int.push_back(adaptive_next(s, s.p.a_init, v0, 0.0));
+      s.a_int.push_back(s.a_int[1] >= af ? af : adaptive_next(s, s.a_int[1], v0, 0.0));
+      s.a_half.assign(1, std::sqrt(s.a_int[0] * s.a_int[1]));
+      s.drift0 = s.cosmo.drift(s.a_int[0], s.a_half[0]);
+      launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+      s.half_drift_done = true;
+    }
+    const int j = s.steps_done;
+    if (j > 0 && s.a_int[j] >= af) return CUBE_DONE;
+    if (j >= s.p.n_steps) throw Error{CUBE_E_STATE, "the adaptive schedule needs more than n_steps steps"};
+    const double ah = s.a_int[j + 1] >= af ? af : std::sqrt(s.a_int[j + 1] * s.a_int[j + 2]);
+    s.a_half.resize(j + 2);
+    s.a_half[j + 1] = ah;
+    s.kicks[j] = s.cosmo.kick(s.a_int[j], s.a_int[j + 1]);
+    s.drifts[j] = s.cosmo.drift(s.a_half[j], ah);
+    launch_deposit(s, s.stream);
+    fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+    launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream, nullptr);
+    double vm = 0.0, gm = 0.0;
+    read_maxima(s, &vm, &gm);
+    s.meas_v.push_back(vm);
+    s.meas_g.push_back(gm);
+    const double an = s.a_int[j + 2];
+    s.a_int.push_back(an >= af ? af : adaptive_next(s, an, vm, gm));
+    s.steps_done++;
+  }
+  return CUBE_OK;
 }
 
 void check_flags(Sim& s) {
@@ -208,6 +287,7 @@ void ic_fields(Sim& s, float** psi, float** wk_out, std::vector<void*>& temps, b
 // when a_final is reached before k steps.
 int enqueue_steps(Sim& s, int k) {
   require_particles(s);
+  if (s.adaptive) return enqueue_adaptive(s, k);
   int rc = CUBE_OK;
   if (s.profiling) {
     for (double& t : s.timings) t = 0.0;
@@ -504,6 +584,11 @@ int cube_step(cube_sim* sim, int32_t k) {
 double cube_scale_factor(const cube_sim* sim) {
   if (!sim) return 0.0;
   const cube::Sim& s = sim->s;
+  if (s.adaptive) {
+    if (s.steps_done == 0 || s.a_int.size() <= (size_t)s.steps_done) return s.p.a_init;
+    if (s.a_int[s.steps_done] >= s.p.a_final) return s.p.a_final;
+    return s.a_half[s.steps_done];
+  }
   if (s.steps_done >= s.p.n_steps) return s.p.a_final;
   if (s.steps_done == 0) return s.p.a_init;
   return s.a_half[s.steps_done];
@@ -648,6 +733,57 @@ int cube_get_cross_power(cube_sim* sa, cube_sim* sb, int32_t nbins, double* k, d
   return CUBE_OK;
 }
 
+int cube_set_adaptive(cube_sim* sim, double eta_v, double eta_a, double eta_e) {
+  if (!sim) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  const bool off = eta_v == 0.0 && eta_a == 0.0 && eta_e == 0.0;
+  if (!off && !(eta_v > 0.0 && eta_a > 0.0 && eta_e > 0.0 && std::isfinite(eta_v) && std::isfinite(eta_a) &&
+                std::isfinite(eta_e)))
+    return cube::fail(sim, Error{CUBE_E_INVALID, "eta_v, eta_a and eta_e must be positive and finite (all 0: off)"});
+  if (s.steps_done > 0 || s.half_drift_done)
+    return cube::fail(sim, Error{CUBE_E_STATE, "adaptive time steps must be chosen before the first step"});
+  CUBE_GUARD(sim, {
+    if (!off && !s.amax) s.amax = static_cast<uint32_t*>(s.dmalloc(2 * sizeof(uint32_t)));
+    if (off && s.amax) {
+      CUBE_HIP(hipStreamSynchronize(s.stream));
+      s.dfree(s.amax);
+      s.amax = nullptr;
+    }
+    s.adaptive = !off;
+    s.eta_v = eta_v;
+    s.eta_a = eta_a;
+    s.eta_e = eta_e;
+    s.config_gen++;
+    cube::build_schedule(s);
+    cube::reset_schedule(s);
+  });
+  return CUBE_OK;
+}
+
+int cube_get_adaptive_log(cube_sim* sim, int32_t max_entries, double* a_int, double* vmax, double* gmax,
+                          int32_t* n_a, int32_t* n_meas) {
+  if (!sim || !n_a || !n_meas || max_entries < 0 || (max_entries > 0 && (!a_int || !vmax || !gmax)))
+    return CUBE_E_INVALID;
+  const cube::Sim& s = sim->s;
+  if (!s.adaptive) return cube::fail(sim, Error{CUBE_E_STATE, "adaptive time steps are off"});
+  *n_a = (int32_t)s.a_int.size();
+  *n_meas = (int32_t)s.meas_v.size();
+  for (int32_t i = 0; i < *n_a && i < max_entries; ++i) a_int[i] = s.a_int[i];
+  for (int32_t i = 0; i < *n_meas && i < max_entries; ++i) {
+    vmax[i] = s.meas_v[i];
+    gmax[i] = s.meas_g[i];
+  }
+  return CUBE_OK;
+}
+
+int cube_get_last_maxima(cube_sim* sim, double* vmax, double* gmax) {
+  if (!sim || !vmax || !gmax) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  if (!s.amax) return cube::fail(sim, Error{CUBE_E_STATE, "adaptive time steps are off"});
+  CUBE_GUARD(sim, { cube::read_maxima(s, vmax, gmax); });
+  return CUBE_OK;
+}
+
 int cube_get_counts(cube_sim* sim, uint32_t* cnt) {
   if (!sim || !cnt) return CUBE_E_INVALID;
   cube::Sim& s = sim->s;
@@ -739,6 +875,8 @@ int cube_set_state(cube_sim* sim, const cube_state_view* in) {
     }
     off[s.nc3] = run;
     if ((int64_t)run != in->n) throw Error{CUBE_E_INVALID, "sum of cell counts differs from n"};
+    if (s.adaptive && in->steps_done != 0)
+      throw Error{CUBE_E_STATE, "an adaptive run restarts from step 0 (its schedule is not part of the checkpoint)"};
     const int c = s.cur;
     const hipStream_t st = s.stream;
     s.n = in->n;

@@ -406,7 +406,10 @@ int cube_batch_step(cube_batch* b, int32_t k) {
   CUBE_BATCH_GUARD(b, {
     std::vector<cube::Sim*> ss;
     for (cube_sim* x : b->boxes) ss.push_back(&x->s);
-    for (cube::Sim* s : ss) cube::require_particles(*s);
+    for (cube::Sim* s : ss) {
+      cube::require_particles(*s);
+      if (s->adaptive) throw Error{CUBE_E_INVALID, "adaptive time steps are not supported in a batch"};
+    }
     const int done = ss[0]->steps_done;
     for (cube::Sim* s : ss)
       if (s->steps_done != done || s->cur != ss[0]->cur)

@@ -87,6 +87,13 @@ struct Sim {
   int cur = 0;
   int config_gen = 0;  // bumped whenever captured step graphs of this simulation become stale
 
+  // adaptive time steps: step j's interval [a_int[j], a_int[j+1]] is chosen from the maxima
+  // measured two steps earlier (meas_*[0]: the state before the first step, [j + 1]: step j)
+  bool adaptive = false;
+  double eta_v = 0.0, eta_a = 0.0, eta_e = 0.0;
+  std::vector<double> meas_v, meas_g;
+  uint32_t* amax = nullptr;  // device: largest |v|^2 and |t|^2 of the last step pass (FP32 bits)
+
   // move scratch
   float* vinv = nullptr;       // nc3 encode scale 1/(sigma sqrt(2/pi))
   uint32_t* mig = nullptr;     // 27 x nc3 counts per (source cell, displacement)
@@ -181,6 +188,8 @@ void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream
 // 1-byte counts into rho1 (nc3 bytes, device) and the counts >= 255 in cell order into over
 // (nc3 entries at most, device); returns the number of the latter
 int64_t launch_counts_u8(Sim& s, uint8_t* rho1, uint32_t* over, hipStream_t st);
+// largest |v|^2 of the current state (uses amax as scratch; synchronises)
+float launch_state_speed2(Sim& s, hipStream_t st);
 // particle IDs 0 .. n-1 in storage order (when IDs are enabled)
 void launch_pid_iota(Sim& s, hipStream_t st);
 void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmodes);

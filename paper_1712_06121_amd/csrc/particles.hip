@@ -248,7 +248,30 @@ struct MoveArgs {
   const void* pid;
   void* pid_n;
   int pid_bytes;
+  // adaptive time steps: when set, the count pass raises amax[0] to the largest |v|^2 after the
+  // kick and amax[1] to the largest |t|^2 of the interpolated gradient (FP32 bit patterns)
+  uint32_t* amax;
 };
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__global__ void k_clear_u32(uint32_t* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// the wave's largest |v|^2 and |t|^2 into the step maxima (non-negative floats order as their bits)
+__device__ __forceinline__ void raise_maxima(uint32_t* amax, float vv, float tq) {
+  vv = wave_max(vv);
+  tq = wave_max(tq);
+  if ((threadIdx.x & 63) == 0) {
+    if (vv > 0.0f) atomicMax(&amax[0], __float_as_uint(vv));
+    if (tq > 0.0f) atomicMax(&amax[1], __float_as_uint(tq));
+  }
+}
 
 // the ID of the particle at storage index p (steps), or of lattice particle li of tile cell s
 // (initial conditions: the lattice index x + N_p (y + N_p z))
@@ -313,6 +336,7 @@ struct Moved {
   int k[3];
   int chi[3];
   bool ok;
+  float vv, tq;  // |v|^2 after the kick and |t|^2 of the interpolated gradient (step passes)
 };
 
 constexpr int DG = F + 2;  // precomputed-gradient tile side: fine cells -1 .. F of the tile
@@ -382,6 +406,8 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
   const int64_t c = (g.cx0 + o[0]) + (int64_t)a.nc * ((g.cy0 + o[1]) + (int64_t)a.nc * (g.cz0 + o[2]));
   float l[3], v[3];
   Moved m;
+  m.vv = 0.0f;
+  m.tq = 0.0f;
   if constexpr (MODE == 2) {
     const int lat[3] = {(int)(li % a.q), (int)((li / a.q) % a.q), (int)(li / (a.q * a.q))};
     const int64_t gx = (int64_t)(g.cx0 + o[0]) * a.q + lat[0];
@@ -437,7 +463,9 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
         }
         const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
         v[d] = v[d] + t * a.kf;
+        m.tq = d == 0 ? t * t : m.tq + t * t;
       }
+      m.vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
@@ -576,6 +604,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
     int key = -1, r = 0;
     long long q[4];
     float vm[3] = {0.f, 0.f, 0.f};
+    float vv = 0.f, tq = 0.f;
     if (active) {
       const int s = find_cell_in(pre, c0, c1, i);
       const uint32_t li = i - pre[s];
@@ -587,7 +616,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
       vm[0] = m.v[0];
       vm[1] = m.v[1];
       vm[2] = m.v[2];
+      vv = m.vv;
+      tq = m.tq;
     }
+    if constexpr (MODE == 0)
+      if (a.amax) raise_maxima(a.amax, vv, tq);
     velocity_moments(vm, q);
     // sum over runs of consecutive lanes with the same (cell, displacement): most particles stay
     // in their cell, so one atomic per run replaces up to 64 conflicting ones
@@ -934,6 +967,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
       if (j0 + 64 < nrow) load_chunk(j + 64);
       float v[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
+      float vv = 0.f, tq = 0.f;
       int ch[3] = {0, 0, 0};
       if (active) {
         const float4 cv = cellv[s];
@@ -974,10 +1008,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           }
           const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
           v[d] = v[d] + t * a.kf;
+          tq = d == 0 ? t * t : tq + t * t;
         }
+        vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
 #pragma unroll
         for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
       }
+      if constexpr (!SCATTER)
+        if (a.amax) raise_maxima(a.amax, vv, tq);
       // new cell, codes, flags (same rules as the generic path)
       int k[3], cq[3];
       bool ok = true;
@@ -1493,6 +1531,13 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   a.pid = s.pid[s.cur];
   a.pid_n = s.pid[nxt];
   a.pid_bytes = s.pid_bytes;
+  // step maxima for adaptive time steps (a small fill kernel clears them: no memset node in
+  // captured graphs, although adaptive simulations are never captured)
+  a.amax = (mode == 0 && s.amax) ? s.amax : nullptr;
+  if (a.amax) {
+    k_clear_u32<<<1, 64, 0, st>>>(s.amax, 2);
+    CUBE_HIP(hipGetLastError());
+  }
   if (mode == 2) {
     a.psi0 = psi[0];
     a.psi1 = psi[1];
@@ -1595,6 +1640,57 @@ void launch_pid_iota(Sim& s, hipStream_t st) {
   if (!s.pid_bytes || s.n == 0) return;
   k_pid_iota<<<(unsigned)((s.n + 255) / 256), 256, 0, st>>>(s.pid[s.cur], s.pid_bytes, s.n);
   CUBE_HIP(hipGetLastError());
+}
+
+// largest |v|^2 of the decoded state (the velocity bound of the first adaptive steps): one thread
+// per particle, its cell found by bisection in the cell offsets
+template <int NNU>
+__global__ void k_state_speed(const void* nu, const uint64_t* off, const float* vc, const float* vs,
+                              const float* tdec, int64_t n, int64_t cap, int64_t nc3, int vhalf, uint32_t* out) {
+  using NT = nu_t<NNU>;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float vv = 0.0f;
+  if (i < n) {
+    int64_t lo = 0, hi = nc3;  // the cell c with off[c] <= i < off[c + 1]
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (off[mid] <= (uint64_t)i) lo = mid;
+      else hi = mid;
+    }
+    const NT* nv = static_cast<const NT*>(nu);
+    float v[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int c = (int)nv[d * cap + i];
+      c = c < -vhalf ? -vhalf : (c > vhalf ? vhalf : c);
+      v[d] = vc[d * nc3 + lo] + vs[lo] * tdec[c + vhalf];
+    }
+    vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+  }
+  vv = wave_max(vv);
+  if ((threadIdx.x & 63) == 0 && vv > 0.0f) atomicMax(out, __float_as_uint(vv));
+}
+
+float launch_state_speed2(Sim& s, hipStream_t st) {
+  k_clear_u32<<<1, 64, 0, st>>>(s.amax, 2);
+  CUBE_HIP(hipGetLastError());
+  if (s.n > 0) {
+    const unsigned grid = (unsigned)((s.n + 255) / 256);
+    const int vh = (s.vm - 1) / 2;
+    if (s.nnu == 1)
+      k_state_speed<1><<<grid, 256, 0, st>>>(s.nu[s.cur], s.off[s.cur], s.vc[s.cur], s.vs[s.cur], s.tdec, s.n,
+                                             s.capacity, s.nc3, vh, s.amax);
+    else
+      k_state_speed<2><<<grid, 256, 0, st>>>(s.nu[s.cur], s.off[s.cur], s.vc[s.cur], s.vs[s.cur], s.tdec, s.n,
+                                             s.capacity, s.nc3, vh, s.amax);
+    CUBE_HIP(hipGetLastError());
+  }
+  uint32_t bits = 0;
+  CUBE_HIP(hipMemcpyAsync(&bits, s.amax, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  CUBE_HIP(hipStreamSynchronize(st));
+  float f;
+  std::memcpy(&f, &bits, sizeof(f));
+  return f;
 }
 
 // 1-byte coarse density (Sec. 2.1): min(count, 255) per cell
