@@ -396,7 +396,7 @@ __device__ __forceinline__ bool new_cell(float ln, float vd, uint32_t* flags, in
   return ok;
 }
 
-template <int NCHI, int NNU, int MODE, bool PRE>
+template <int NCHI, int NNU, int MODE, bool PRE, bool MEAS = false>
 __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* ph, const float* gd, int s, int64_t p,
                                                uint32_t li, const TileGeom& g) {
   using CT = chi_t<NCHI>;
@@ -463,9 +463,9 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
         }
         const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
         v[d] = v[d] + t * a.kf;
-        m.tq = d == 0 ? t * t : m.tq + t * t;
+        if constexpr (MEAS) m.tq = d == 0 ? t * t : m.tq + t * t;
       }
-      m.vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+      if constexpr (MEAS) m.vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
@@ -578,7 +578,7 @@ struct MoveLds {
 };
 
 // at least six wavefronts per SIMD (three 512-thread workgroups per CU): at most 80 VGPRs
-template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH, bool MEAS = false>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k_move_count(MoveArgs a) {
   resolve_factors(a);
   using L = MoveLds<MODE, PRE>;
@@ -609,7 +609,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
       const int s = find_cell_in(pre, c0, c1, i);
       const uint32_t li = i - pre[s];
       const int64_t p = (int64_t)start[s] + li;
-      const Moved m = move_particle<NCHI, NNU, MODE, PRE>(a, ph, gd, s, p, li, g);
+      const Moved m = move_particle<NCHI, NNU, MODE, PRE, MEAS>(a, ph, gd, s, p, li, g);
       const int dcode = (m.k[2] + 1) * 9 + (m.k[1] + 1) * 3 + (m.k[0] + 1);
       key = s * 27 + dcode;
       r = (s % T + 1 + m.k[0]) + RG * ((s / T) % T + 1 + m.k[1]) + RG * RG * (s / (T * T) + 1 + m.k[2]);
@@ -619,8 +619,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
       vv = m.vv;
       tq = m.tq;
     }
-    if constexpr (MODE == 0)
-      if (a.amax) raise_maxima(a.amax, vv, tq);
+    if constexpr (MEAS) raise_maxima(a.amax, vv, tq);
     velocity_moments(vm, q);
     // sum over runs of consecutive lanes with the same (cell, displacement): most particles stay
     // in their cell, so one atomic per run replaces up to 64 conflicting ones
@@ -803,22 +802,48 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
 template <unsigned CTRL, unsigned ROWS = 0xF>
 __device__ __forceinline__ unsigned long long dpp_add_u64(unsigned long long v) {
   const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  const uint32_t l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xF, false);
-  const uint32_t h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xF, false);
-  return v + (((unsigned long long)h2 << 32) | l2);
+  uint32_t l2, h2;
+  if constexpr (ROWS == 0xF) {
+    // every row written: lanes without a source read 0 (bound control), no old value needed
+    l2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, CTRL, 0xF, 0xF, true);
+    h2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, CTRL, 0xF, 0xF, true);
+  } else {
+    l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xF, false);
+    h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xF, false);
+  }
+  unsigned int carry;
+  const unsigned int rl = __builtin_addc(lo, l2, 0u, &carry);
+  const unsigned int rh = __builtin_addc(hi, h2, carry, &carry);
+  return ((unsigned long long)rh << 32) | rl;
 }
+
+// One step of the 64-bit inclusive scan: v += (v of the lane DPP selects, 0 where there is none;
+// rows outside the row mask unchanged), as a carry-propagating add whose first operand is read
+// through DPP. The s_nop before each step covers the two wait states a DPP read needs after a VALU
+// write of the same register; the one after the block keeps later DPP reads of lo / hi safe.
+#define CUBE_DPP_ADD64(lo, hi, CTRL, RMASK)                                                        \
+  asm volatile("s_nop 1\n\t"                                                                     \
+               "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL " row_mask:" RMASK                        \
+               " bank_mask:0xf bound_ctrl:1\n\t"                                                 \
+               "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL " row_mask:" RMASK                  \
+               " bank_mask:0xf bound_ctrl:1\n\t"                                                 \
+               "s_nop 1"                                                                          \
+               : "+v"(lo), "+v"(hi)                                                               \
+               :                                                                                  \
+               : "vcc")
 
 // inclusive prefix sum over the 64 lanes (every lane active): shifts by 1, 2, 4, 8 inside each
 // row of 16 lanes, then the totals of rows 0 and 2 into rows 1 and 3, then that of rows 0-1 into
 // rows 2 and 3
 __device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long v) {
-  v = dpp_add_u64<0x111>(v);        // row_shr:1
-  v = dpp_add_u64<0x112>(v);        // row_shr:2
-  v = dpp_add_u64<0x114>(v);        // row_shr:4
-  v = dpp_add_u64<0x118>(v);        // row_shr:8
-  v = dpp_add_u64<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  v = dpp_add_u64<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
-  return v;
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  CUBE_DPP_ADD64(lo, hi, "row_shr:1", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_shr:2", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_shr:4", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_shr:8", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_bcast:15", "0xa");
+  CUBE_DPP_ADD64(lo, hi, "row_bcast:31", "0xc");
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 __device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int lane) {
@@ -842,7 +867,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
   return t;
 }
 
-template <int NCHI, int NNU, bool SCATTER>
+template <int NCHI, int NNU, bool SCATTER, bool MEAS = false>
 // two 1024-thread workgroups per CU: at most 64 VGPRs
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_move_dense(MoveArgs a) {
   resolve_factors(a);
@@ -1008,14 +1033,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           }
           const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
           v[d] = v[d] + t * a.kf;
-          tq = d == 0 ? t * t : tq + t * t;
+          if constexpr (MEAS) tq = d == 0 ? t * t : tq + t * t;
         }
-        vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+        if constexpr (MEAS) vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
 #pragma unroll
         for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
       }
-      if constexpr (!SCATTER)
-        if (a.amax) raise_maxima(a.amax, vv, tq);
+      if constexpr (MEAS) raise_maxima(a.amax, vv, tq);
       // new cell, codes, flags (same rules as the generic path)
       int k[3], cq[3];
       bool ok = true;
@@ -1557,7 +1581,9 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   const bool tile_scatter = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 2));
 #define CUBE_COUNT(X, V)                                                                        \
   do {                                                                                          \
-    if (tile_count) k_move_dense<X, V, false><<<grid, 1024, 0, st>>>(a);                         \
+    if (tile_count && a.amax) k_move_dense<X, V, false, true><<<grid, 1024, 0, st>>>(a);         \
+    else if (tile_count) k_move_dense<X, V, false><<<grid, 1024, 0, st>>>(a);                    \
+    else if (mode == 0 && a.amax) k_move_count<X, V, 0, false, 512, true><<<grid, 512, 0, st>>>(a); \
     else if (mode == 0) k_move_count<X, V, 0, false, 512><<<grid, 512, 0, st>>>(a);              \
     else if (mode == 1) k_move_count<X, V, 1, false, 256><<<grid, 256, 0, st>>>(a);              \
     else k_move_count<X, V, 2, false, 256><<<grid, 256, 0, st>>>(a);                             \
