@@ -126,6 +126,11 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   __shared__ uint32_t pre[DRC + 1];
   __shared__ uint64_t start[DRC];
   __shared__ uint32_t wsum[BLK / 64];
+  // owner[k]: the source cell holding layer particle k << osh (a sparse index into pre, so that a
+  // particle's cell is found by a short forward scan instead of a binary search)
+  constexpr int NOWN = 1024;
+  static_assert(DRC < 256, "cell indices fit a byte");
+  __shared__ uint8_t owner[NOWN];
   const unsigned lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   const unsigned bxy = lb % gridDim.x, bz = lb / gridDim.x;
   const int cx0 = (bxy % a.nt) * DTX, cy0 = (bxy / a.nt) * DTX;
@@ -146,11 +151,19 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
     }
     const uint32_t total = block_exclusive_scan(cntv, pre, DRC, wsum);
     const uint32_t q64 = total / 64;
+    int osh = 4;
+    while ((total >> osh) >= (uint32_t)NOWN) ++osh;
+    if (threadIdx.x < DRC) {
+      const uint32_t lo = pre[threadIdx.x], hi = pre[threadIdx.x + 1];
+      for (uint32_t k = (lo + (1u << osh) - 1) >> osh; (k << osh) < hi; ++k) owner[k] = (uint8_t)threadIdx.x;
+    }
+    __syncthreads();
     for (uint32_t it = threadIdx.x; it < total; it += BLK) {
       // interleaved: lane l of the w-th group of 64 takes particle l * (total / 64) + w, so the lanes
       // of one wavefront hold particles of different cells (a bijection on [0, 64 * (total / 64)))
       const uint32_t i = (a.interleave && it < 64 * q64) ? (it % 64) * q64 + it / 64 : it;
-      const int s = find_cell(pre, DRC, i);
+      int s = owner[i >> osh];
+      while (pre[s + 1] <= i) ++s;
       const int64_t p = (int64_t)start[s] + (i - pre[s]);
       const int sl[3] = {s % DR - 1, s / DR - 1, sz};
       const int ch[3] = {(int)cx[p], (int)cy[p], (int)cz[p]};
