@@ -266,6 +266,11 @@ struct MoveArgs {
   uint32_t* amax;
 };
 
+// number of lanes below this one in the wave mask m
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 __device__ __forceinline__ float wave_max(float x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
@@ -997,6 +1002,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       }
     };
     load_chunk(lane);
+    uint32_t scnt[T] = {0u, 0u, 0u, 0u};  // scatter: stayers ranked so far per cell of the row
     for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
       const uint32_t j = j0 + lane;
       const bool active = j < nrow;
@@ -1111,23 +1117,47 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           }
         }
       } else {
-        // lanes with the same (cell of the row, displacement): rank among them in storage order
-        const int key = (ci << 5) | dcode;
-        unsigned long long peers = __ballot(active);
+        // rank among the lanes with the same (cell of the row, displacement), in storage order;
+        // only this wave ranks particles of the row's cells. Stayers: a running count per cell of
+        // the row, kept by the wave. Movers (few): one pass per distinct key, counters in LDS.
+        uint32_t rin = 0, gbase = 0;
+        const bool stay = active && dcode == 13;
+        const unsigned long long smask = __ballot(stay);
+        const int cfirst = __builtin_amdgcn_readfirstlane(ci);
+        const uint32_t jend = nrow - j0 < 64u ? nrow - j0 : 64u;  // active lanes
+        const int clast = __builtin_amdgcn_readlane(ci, (int)jend - 1);
+        const uint32_t bnd[5] = {0u, p1, p2, p3, nrow};
 #pragma unroll
-        for (int b = 0; b < 7; ++b) {
-          const bool bit = (key >> b) & 1;
-          const unsigned long long bb = __ballot(active && bit);
-          peers &= bit ? bb : ~bb;
+        for (int cc = 0; cc < T; ++cc) {
+          if (cc < cfirst || cc > clast) continue;
+          // lanes [la, le) (wave-uniform)
+          const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)(bnd[cc] > j0 ? bnd[cc] - j0 : 0u));
+          const uint32_t le =
+              (uint32_t)__builtin_amdgcn_readfirstlane((int)(bnd[cc + 1] - j0 < jend ? bnd[cc + 1] - j0 : jend));
+          if (la >= le) continue;
+          const unsigned long long seg = (le == 64u ? ~0ull : ((1ull << le) - 1ull)) & ~((1ull << la) - 1ull);
+          const unsigned long long m = smask & seg;
+          if (stay && ci == cc) {
+            rin = lanes_below(m);
+            gbase = scnt[cc];
+          }
+          scnt[cc] += (uint32_t)__popcll(m);
         }
-        const int rin = __popcll(peers & lt);
-        const int leader = active ? __ffsll((long long)peers) - 1 : lane;
-        uint32_t gbase = 0;
-        if (active && rin == 0) {
-          gbase = grp[s * 27 + dcode];
-          grp[s * 27 + dcode] = gbase + (uint32_t)__popcll(peers);
+        const int key = (ci << 5) | dcode;
+        unsigned long long todo = __ballot(active && !stay);
+        while (todo) {
+          const int leader = (int)__builtin_ctzll(todo);
+          const int lk = __builtin_amdgcn_readlane(key, leader);
+          const unsigned long long m = __ballot(active && key == lk);
+          const int gi = (s0 + (lk >> 5)) * 27 + (lk & 31);
+          const uint32_t b0 = grp[gi];
+          if (active && key == lk) {
+            rin = lanes_below(m);
+            gbase = b0;
+          }
+          if (lane == leader) grp[gi] = b0 + (uint32_t)__popcll(m);
+          todo &= ~m;
         }
-        gbase = (uint32_t)__shfl((int)gbase, leader, 64);
         if (active) {
           const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
           const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
