@@ -25,6 +25,13 @@ if ROOT not in sys.path:
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# 32-bit vector ALU lane-operations per second without packed math or FMA: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (the move passes use neither: packed FP32 is disabled in the build and the
+# arithmetic contract forbids contraction)
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# arithmetic operations per particle that the method itself needs in each move pass (decode,
+# CIC weights, gradient interpolation, kick, drift, new cell, moments / encode)
+ALGO_OPS_PER_PARTICLE = {"move_count": 136, "move_scatter": 147}
 KERNELS = ("deposit", "fft_x", "fft_y", "fft_z_green", "fft_y_inv", "fft_x_inv", "move_count", "link_scan",
            "move_scatter")
 
@@ -67,6 +74,25 @@ def measured_traffic(kernel: str):
                 return None
             kib = float(rec["fetch_kib"]) * float(rec["fetch_scale"]) + float(rec["write_kib"]) * float(rec["write_scale"])
             return kib * 1024.0
+    return None
+
+
+def measured_valu(kernel: str):
+    """VALU instructions per launch of `kernel` from the committed rocprofv3 SQ counter summary, or
+    None when there is none or the kernel source has changed since."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_instructions.md"))):
+        for line in open(path):
+            if not line.startswith("valu-record:"):
+                continue
+            rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+            if rec.get("kernel") != kernel:
+                continue
+            src = os.path.join(ROOT, rec["source"])
+            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+                return None
+            return float(rec["valu_insts"])
     return None
 
 
@@ -335,6 +361,39 @@ def main() -> int:
     ab = algorithmic_bytes(cfg)
     dom = max(KERNELS, key=lambda k: ms[k])
     achieved = ab[dom] / (ms[dom] * 1e-3) / 1e9
+    full = args.workload == "c3_pm2048"
+    hbm_view = {
+        "bound": "hbm",
+        "kernel": dom,
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": measured_traffic(dom) if full else None,
+        "algorithmic_bytes_per_launch": ab[dom],
+        "avg_launch_ms": ms[dom],
+    }
+    if dom in ALGO_OPS_PER_PARTICLE:
+        # the move passes issue vector instructions back to back (about one per SIMD every 4 cycles):
+        # they are bound by the vector ALU, not by HBM
+        ops = ALGO_OPS_PER_PARTICLE[dom] * cfg["np_side"] ** 3
+        tops = ops / (ms[dom] * 1e-3) / 1e12
+        valu = measured_valu(dom) if full else None
+        roofline = {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": tops,
+            "peak": ALU_PEAK_TOPS,
+            "unit": "TOP/s",
+            "frac": tops / ALU_PEAK_TOPS,
+            "traffic": hbm_view["traffic"],
+            "algorithmic_ops_per_launch": ops,
+            "avg_launch_ms": ms[dom],
+            "valu_instructions_per_launch": valu,
+            "cycles_per_valu_issue_per_simd": (ms[dom] * 1e-3 * 2.4e9 / (valu / 1024)) if valu else None,
+        }
+    else:
+        roofline = hbm_view
     step_bytes = sum(ab.values())
     step_ms = sum(ms.values())
     k_step = elapsed / args.steps
@@ -370,17 +429,8 @@ def main() -> int:
             "sigma": "per-cell",
             "variants": sim.variant,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom) if args.workload == "c3_pm2048" else None,
-            "algorithmic_bytes_per_launch": ab[dom],
-            "avg_launch_ms": ms[dom],
-        },
+        "roofline": roofline,
+        "roofline_hbm": hbm_view,
         "step_roofline": {
             "algorithmic_bytes": step_bytes,
             "achieved_GBs": step_bytes / k_step / 1e9,
