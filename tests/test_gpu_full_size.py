@@ -10,6 +10,8 @@ particles, so the checks are properties that hold at any size:
   3/2 Omega_m times the displacement, so the leapfrog of one mode can be followed exactly); the
   same modes are compared, so there is no cosmic variance in the ratio.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -80,3 +82,49 @@ def test_full_size_mass_spectrum_and_growth(lib):
     print(f"a = {a1:.4f} after {steps} steps: P ratio {np.round(growth, 4)}, linear leapfrog {g * g:.4f}, "
           f"(D(a)/D(a0))^2 {(cosmo.D(a1) / cosmo.D(cfg['a_init'])) ** 2:.4f}")
     assert np.all(np.abs(growth / (g * g) - 1) < 0.01)
+
+
+@pytest.mark.parametrize("variant", [dict(fft_z_layout=0), dict(fft_col_width=8, fft_z_layout=1, fft_z_width=4)])
+def test_full_size_poisson_on_plane_waves(lib, variant):
+    """The 2048^3 Poisson solve (the five FFT passes with the Green's function, in the mesh layout and
+    in the z-contiguous layout the autotuner picks at this size) on a density of plane waves, whose
+    potential is known exactly: phi_k = -(3/2) Omega_m delta_k / |k|^2 with k = 2 pi n / N_m per
+    fine cell (Sec. 2.3.3). Checked on 2e5 sampled cells."""
+    import torch
+    torch.cuda.empty_cache()
+    cfg = synth.WORKLOADS[NAME]
+    need = lib.footprint(**cfg) + (40 << 30)
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    nm, om = cfg["nm_side"], cfg["omega_m"]
+    # (n_x, n_y, n_z), amplitude, phase: low, intermediate and near-Nyquist modes, one off-axis
+    waves = [((3, 0, 0), 0.5, 0.3), ((0, 517, 0), 0.2, 1.1), ((0, 0, 1023), 0.1, -0.7), ((5, -7, 0), 0.3, 2.0)]
+    i = torch.arange(nm, dtype=torch.float64)
+
+    def c1(n, amp, ph):
+        return (amp * torch.cos(2 * math.pi * n * i / nm + ph)).float()
+
+    delta = torch.empty((nm, nm, nm), dtype=torch.float32)  # [z, y, x], host memory
+    delta.copy_(c1(3, 0.5, 0.3)[None, None, :].expand(nm, nm, nm))
+    delta += c1(517, 0.2, 1.1)[None, :, None]
+    delta += c1(1023, 0.1, -0.7)[:, None, None]
+    # cos(a x + b y + ph) = cos(a x) cos(b y + ph) - sin(a x) sin(b y + ph)
+    ax, by = 2 * math.pi * 5 * i / nm, 2 * math.pi * -7 * i / nm + 2.0
+    delta += (0.3 * (torch.cos(ax)[None, :] * torch.cos(by)[:, None] - torch.sin(ax)[None, :] * torch.sin(by)[:, None])).float()[None]
+    with lib.Sim(**cfg) as sim:
+        sim.set_variant(**variant)
+        sim.set_mesh(delta.numpy())
+        del delta
+        sim.stage_solve()
+        phi = torch.from_numpy(sim.get_mesh())
+    g = np.random.default_rng(31)
+    z, y, x = (g.integers(0, nm, size=200000) for _ in range(3))
+    want = np.zeros(len(x))
+    for (nx, ny, nz), amp, ph in waves:
+        k2 = (2 * math.pi / nm) ** 2 * (nx * nx + ny * ny + nz * nz)
+        want += -1.5 * om * amp * np.cos(2 * math.pi * (nx * x + ny * y + nz * z) / nm + ph) / k2
+    got = phi[torch.from_numpy(z), torch.from_numpy(y), torch.from_numpy(x)].double().numpy()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"variant {variant}: max |phi - exact| / max |phi| = {err:.2e}")
+    assert err < 1e-5
