@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
 template <int N, int BX>
 struct ColCfg {
   static constexpr int NQ = N * BX / 2;
-  static constexpr int BLOCK = (N >= 2048) ? 512 : (NQ % 256 == 0 ? 256 : (NQ % 128 == 0 ? 128 : 64));
+  static constexpr int BLOCK = (N >= 2048) ? (BX >= 8 ? 1024 : 512) : (NQ % 256 == 0 ? 256 : (NQ % 128 == 0 ? 128 : 64));
 };
 constexpr int col_bx_default(int n) { return n >= 1024 ? 8 : 16; }
 constexpr int col_bx_pitch(int n) { return n >= 1024 ? 8 : 16; }
