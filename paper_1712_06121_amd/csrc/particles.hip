@@ -138,6 +138,26 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   const int cz1 = min(cz0 + a.zc, a.nc);
   const int pz0 = 4 * cz0, pz1 = 4 * cz1;  // owned fine planes [pz0, pz1)
   for (int i = threadIdx.x; i < NSLOT * DF * DF; i += BLK) rho[i] = 0ull;
+  // 32-bit accumulators: a fine cell receives mass only from particles of the (at most 8) coarse
+  // cells around it, each weighing 2^(3 SH) in total; with 1-byte codes and at most 255 particles
+  // in every source cell of this workgroup the sum stays below 8 * 255 * 2^21 < 2^32
+  __shared__ uint32_t smax;
+  if (threadIdx.x == 0) smax = 0u;
+  __syncthreads();
+  if constexpr (NCHI == 1) {
+    uint32_t m = 0u;
+    const int ncell = DRC * (cz1 - cz0 + 2);
+    for (int i = threadIdx.x; i < ncell; i += BLK) {
+      const int t = i % DRC, sz = cz0 - 1 + i / DRC;
+      const int sx = t % DR - 1, sy = t / DR - 1;
+      const uint32_t c = a.cnt[wrapi(cx0 + sx, a.nc) + (int64_t)a.nc * (wrapi(cy0 + sy, a.nc) + (int64_t)a.nc * wrapi(sz, a.nc))];
+      m = c > m ? c : m;
+    }
+    atomicMax(&smax, m);
+  }
+  __syncthreads();
+  const bool narrow = NCHI == 1 && smax <= 255u;
+  uint32_t* rho32 = reinterpret_cast<uint32_t*>(rho);
   const CT* cx = static_cast<const CT*>(a.chi);
   const CT* cy = cx + a.cap;
   const CT* cz = cy + a.cap;
@@ -158,6 +178,8 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
       for (uint32_t k = (lo + (1u << osh) - 1) >> osh; (k << osh) < hi; ++k) owner[k] = (uint8_t)threadIdx.x;
     }
     __syncthreads();
+    auto deposit_layer = [&](auto* acc) {
+    using A = typename std::remove_pointer<decltype(acc)>::type;
     for (uint32_t it = threadIdx.x; it < total; it += BLK) {
       // interleaved: lane l of the w-th group of 64 takes particle l * (total / 64) + w, so the lanes
       // of one wavefront hold particles of different cells (a bijection on [0, 64 * (total / 64)))
@@ -192,13 +214,15 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
           for (int dx = 0; dx < 2; ++dx) {
             const int x = i0[0] + dx;
             if (x < 0 || x >= DF) continue;
-            const unsigned long long w = NCHI == 1 ? (unsigned long long)(wzy * wx2[dx])
-                                                   : (unsigned long long)wzy * (unsigned long long)wx2[dx];
-            atomicAdd(&rho[sb + y * DF + x], w);
+            const A w = NCHI == 1 ? (A)(wzy * wx2[dx]) : (A)((unsigned long long)wzy * (unsigned long long)wx2[dx]);
+            atomicAdd(&acc[sb + y * DF + x], w);
           }
         }
       }
     }
+    };
+    if (narrow) deposit_layer(rho32);
+    else deposit_layer(rho);
     __syncthreads();
     // planes completed by this layer
     const int f0 = max(4 * sz - 1, pz0), f1 = min(4 * sz + 2, pz1 - 1);
@@ -207,8 +231,14 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
       const int pz = f0 + i / (DF * DF), e = i % (DF * DF);
       const int y = e / DF, x = e - y * DF;
       const int idx = slot_of(pz) * DF * DF + e;
-      const double r = (double)rho[idx];
-      rho[idx] = 0ull;
+      double r;
+      if (narrow) {
+        r = (double)rho32[idx];
+        rho32[idx] = 0u;
+      } else {
+        r = (double)rho[idx];
+        rho[idx] = 0ull;
+      }
       a.mesh[((int64_t)pz * a.nm + (4 * cy0 + y)) * a.pitch_f + (4 * cx0 + x)] = (float)(r * a.inv_mean - 1.0);
     }
     __syncthreads();

@@ -59,12 +59,15 @@ def np_for(nm):
     return next(p for p in (32, 48, 64, 96, 128, 192, 256) if p % (nm // 4) == 0)
 
 
+@pytest.mark.parametrize("clumps", [0.4, 0.0])
 @pytest.mark.parametrize("nchi", [1, 2])
 @pytest.mark.parametrize("nm", [32, 64, 96, 128])
-def test_deposit_bit_exact(Sim, nchi, nm):
+def test_deposit_bit_exact(Sim, nchi, nm, clumps):
+    # clumped clouds put hundreds to thousands of particles in a coarse cell (64-bit LDS sums);
+    # without clumps every cell holds fewer than 255 (the 32-bit sums of 1-byte codes)
     nc = nm // 4
     n = 5 * nm**3 // 16 + 7
-    x, v = synth.particle_cloud(31 + nm, n, nm, clump_frac=0.4)
+    x, v = synth.particle_cloud(31 + nm, n, nm, clump_frac=clumps)
     ref = twin.load(x, v, nc, nchi, 1)
     with Sim(np_for(nm), nm, 100.0, x_bytes=nchi, capacity=n) as sim:
         sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
