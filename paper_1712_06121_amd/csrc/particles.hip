@@ -68,6 +68,74 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* out, int n, uint3
   return total;
 }
 
+template <unsigned CTRL, unsigned ROWS = 0xF>
+__device__ __forceinline__ unsigned long long dpp_add_u64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  uint32_t l2, h2;
+  if constexpr (ROWS == 0xF) {
+    // every row written: lanes without a source read 0 (bound control), no old value needed
+    l2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, CTRL, 0xF, 0xF, true);
+    h2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, CTRL, 0xF, 0xF, true);
+  } else {
+    l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xF, false);
+    h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xF, false);
+  }
+  unsigned int carry;
+  const unsigned int rl = __builtin_addc(lo, l2, 0u, &carry);
+  const unsigned int rh = __builtin_addc(hi, h2, carry, &carry);
+  return ((unsigned long long)rh << 32) | rl;
+}
+
+// One step of the 64-bit inclusive scan: v += (v of the lane DPP selects, 0 where there is none;
+// rows outside the row mask unchanged), as a carry-propagating add whose first operand is read
+// through DPP. The s_nop before each step covers the two wait states a DPP read needs after a VALU
+// write of the same register; the one after the block keeps later DPP reads of lo / hi safe.
+#define CUBE_DPP_ADD64(lo, hi, CTRL, RMASK)                                                        \
+  asm volatile("s_nop 1\n\t"                                                                     \
+               "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL " row_mask:" RMASK                        \
+               " bank_mask:0xf bound_ctrl:1\n\t"                                                 \
+               "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL " row_mask:" RMASK                  \
+               " bank_mask:0xf bound_ctrl:1\n\t"                                                 \
+               "s_nop 1"                                                                          \
+               : "+v"(lo), "+v"(hi)                                                               \
+               :                                                                                  \
+               : "vcc")
+
+// inclusive prefix sum over the 64 lanes (every lane active): shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes, then the totals of rows 0 and 2 into rows 1 and 3, then that of rows 0-1 into
+// rows 2 and 3
+__device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  CUBE_DPP_ADD64(lo, hi, "row_shr:1", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_shr:2", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_shr:4", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_shr:8", "0xf");
+  CUBE_DPP_ADD64(lo, hi, "row_bcast:15", "0xa");
+  CUBE_DPP_ADD64(lo, hi, "row_bcast:31", "0xc");
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// sum over the 64 lanes (every lane active), returned to all lanes
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+  v = dpp_add_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add_u64<0x141>(v);  // row_half_mirror
+  v = dpp_add_u64<0x140>(v);  // row_mirror: every lane holds its 16-lane row sum
+  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+  unsigned long long t = 0;
+#pragma unroll
+  for (int r = 15; r < 64; r += 16)
+    t += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, r) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
+  return t;
+}
+
 __device__ __forceinline__ int find_cell(const uint32_t* pre, int ncell, uint32_t i) {
   int lo = 0, hi = ncell;
   while (hi - lo > 1) {
@@ -673,19 +741,17 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
     // in their cell, so one atomic per run replaces up to 64 conflicting ones
     const int kprev = __shfl_up(key, 1, 64);
     const bool head = lane == 0 || kprev != key;
-    int st = head ? lane : 0;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(st, o, 64);
-      if (lane >= o && y > st) st = y;
-    }
+    // st: the first lane of this lane's run, the highest run head at or below it (lane 0 is one)
+    const unsigned long long heads = __ballot(head);
+    const int st = 63 - __clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
+    // run sums from one prefix scan: the scan at the lane minus the scan before the run
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
-#pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const long long y = __shfl_up(q[d], o, 64);
-        if (lane - o >= st) q[d] += y;
-      }
+      const unsigned long long ps = wave_scan_u64((unsigned long long)q[d]);
+      const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)ps, st - 1, 64);
+      const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(ps >> 32), st - 1, 64);
+      const unsigned long long before = st > 0 ? (((unsigned long long)hi << 32) | lo) : 0ull;
+      q[d] = (long long)(ps - before);
     }
     const int knext = __shfl_down(key, 1, 64);
     const bool tail = lane == 63 || knext != key;
@@ -847,73 +913,6 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
 // (the large majority) are summed with one cross-lane reduction; particles of a cell are visited
 // in storage order by a single wave, which makes the running rank per displacement exact.
 // ---------------------------------------------------------------------------------------------
-template <unsigned CTRL, unsigned ROWS = 0xF>
-__device__ __forceinline__ unsigned long long dpp_add_u64(unsigned long long v) {
-  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  uint32_t l2, h2;
-  if constexpr (ROWS == 0xF) {
-    // every row written: lanes without a source read 0 (bound control), no old value needed
-    l2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, CTRL, 0xF, 0xF, true);
-    h2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, CTRL, 0xF, 0xF, true);
-  } else {
-    l2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xF, false);
-    h2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi, CTRL, ROWS, 0xF, false);
-  }
-  unsigned int carry;
-  const unsigned int rl = __builtin_addc(lo, l2, 0u, &carry);
-  const unsigned int rh = __builtin_addc(hi, h2, carry, &carry);
-  return ((unsigned long long)rh << 32) | rl;
-}
-
-// One step of the 64-bit inclusive scan: v += (v of the lane DPP selects, 0 where there is none;
-// rows outside the row mask unchanged), as a carry-propagating add whose first operand is read
-// through DPP. The s_nop before each step covers the two wait states a DPP read needs after a VALU
-// write of the same register; the one after the block keeps later DPP reads of lo / hi safe.
-#define CUBE_DPP_ADD64(lo, hi, CTRL, RMASK)                                                        \
-  asm volatile("s_nop 1\n\t"                                                                     \
-               "v_add_co_u32_dpp %0, vcc, %0, %0 " CTRL " row_mask:" RMASK                        \
-               " bank_mask:0xf bound_ctrl:1\n\t"                                                 \
-               "v_addc_co_u32_dpp %1, vcc, %1, %1, vcc " CTRL " row_mask:" RMASK                  \
-               " bank_mask:0xf bound_ctrl:1\n\t"                                                 \
-               "s_nop 1"                                                                          \
-               : "+v"(lo), "+v"(hi)                                                               \
-               :                                                                                  \
-               : "vcc")
-
-// inclusive prefix sum over the 64 lanes (every lane active): shifts by 1, 2, 4, 8 inside each
-// row of 16 lanes, then the totals of rows 0 and 2 into rows 1 and 3, then that of rows 0-1 into
-// rows 2 and 3
-__device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long v) {
-  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  CUBE_DPP_ADD64(lo, hi, "row_shr:1", "0xf");
-  CUBE_DPP_ADD64(lo, hi, "row_shr:2", "0xf");
-  CUBE_DPP_ADD64(lo, hi, "row_shr:4", "0xf");
-  CUBE_DPP_ADD64(lo, hi, "row_shr:8", "0xf");
-  CUBE_DPP_ADD64(lo, hi, "row_bcast:15", "0xa");
-  CUBE_DPP_ADD64(lo, hi, "row_bcast:31", "0xc");
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ unsigned long long read_lane_u64(unsigned long long v, int lane) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// sum over the 64 lanes (every lane active), returned to all lanes
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-  v = dpp_add_u64<0xB1>(v);   // quad_perm [1,0,3,2]
-  v = dpp_add_u64<0x4E>(v);   // quad_perm [2,3,0,1]
-  v = dpp_add_u64<0x141>(v);  // row_half_mirror
-  v = dpp_add_u64<0x140>(v);  // row_mirror: every lane holds its 16-lane row sum
-  const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-  unsigned long long t = 0;
-#pragma unroll
-  for (int r = 15; r < 64; r += 16)
-    t += ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, r) << 32) |
-         (uint32_t)__builtin_amdgcn_readlane((int)lo, r);
-  return t;
-}
 
 template <int NCHI, int NNU, bool SCATTER, bool MEAS = false>
 // two 1024-thread workgroups per CU: at most 64 VGPRs
