@@ -6,7 +6,8 @@ CUBE is a lossy compression of plain PM (oracle.pm). The lossy part -- encoding,
 storage order, integer density -- has to be reproduced bit-exactly by the GPU from identical
 inputs, so this module spells out one fixed sequence of IEEE operations for it, written from
 the paper's equations. Every FP32 operation is a separate numpy float32 operation
-(round-to-nearest, no fused multiply-add); every FP64 operation likewise in float64.
+(round-to-nearest) except the fused multiply-adds named below, which round once (fma32, computed
+exactly); every FP64 operation likewise in float64.
 
 State (cell-ordered storage, Sec. 2.1):
   cnt[c]      particles per coarse cell, c = x + N_c (y + N_c z)
@@ -19,15 +20,16 @@ Units: fine-mesh cells, ratio R = N_m / N_c = 4, H0 = 1, momentum p = a^2 dx/dt.
 Definitions (the device contract):
 * position decode, Eq. (x): local offset in fine cells l = (2 chi_u + 1) 2^{1 - 8 n_chi}, chi_u
   the stored unsigned code; global fine position 4 c + l.
-* velocity decode, Eq. (v): v = vc + vs * T[nu] with T[nu] = FP32(tan(pi nu / M)).
+* velocity decode, Eq. (v): v = fma(vs, T[nu], vc) with T[nu] = FP32(tan(pi nu / M)).
 * integer CIC (Sec. 3 CIC, cell centres at i + 1/2): in units of 2^{1-8 n_chi} fine cells the
   particle sits at P = c 2^{8 n_chi + 1} + 2 chi_u + 1; Q = P - 2^{8 n_chi - 2};
   i0 = Q >> (8 n_chi - 1), f = Q mod 2^{8 n_chi - 1}; weights (2^{8 n_chi-1} - f, f), the mass
   of a particle is 2^{3 (8 n_chi - 1)}; sums are exact int64.
   delta = FP32( FP64(rho) * (N_m^3 / (N_p 2^{3(8 n_chi - 1)})) - 1 ).
 * gradient, 4-point: D = 8 (phi[i+1] - phi[i-1]) - (phi[i+2] - phi[i-2]) (FP32, force -D/12).
-* interpolation: r = wx0*D(0) + wx1*D(1) along x, then y, then z (FP32, exact dyadic weights).
-* kick: v' = v + t * kf, kf = FP32(-K/12); drift: l' = l + v' * df, df = FP32(Delta).
+* interpolation: r = fma(wx1, D(1), wx0*D(0)) along x, then y, then z (FP32, exact dyadic
+  weights).
+* kick: v' = fma(t, kf, v), kf = FP32(-K/12); drift: l' = fma(v', df, l), df = FP32(Delta).
 * new cell: k = -1 if l' < 0, +1 if l' >= 4, else 0 (|l'| beyond one cell is a CFL error);
   l'' = l' - 4k; chi_u' = clamp(floor(l'' 2^{8 n_chi - 2}), 0, 2^{8 n_chi} - 1).
 * moments per new cell (int64): n, S1_d = sum rint(v'_d 2^32), S2 = sum_d rint(v'_d^2 2^24).
@@ -52,6 +54,24 @@ import numpy as np
 
 R = 4
 F32 = np.float32
+
+
+def fma32(a, b, c):
+    """a * b + c rounded once to FP32 (the device's fused multiply-add), elementwise.
+
+    The product of two FP32 values is exact in FP64; the FP64 sum is rounded to odd (the exact
+    error of the sum, from TwoSum, tells whether it was inexact and on which side), and rounding an
+    odd-rounded value with at least two extra bits to FP32 gives the correctly rounded result."""
+    a = np.asarray(a, np.float32).astype(np.float64)
+    b = np.asarray(b, np.float32).astype(np.float64)
+    c = np.asarray(c, np.float32).astype(np.float64)
+    p = a * b
+    s = p + c
+    bb = s - p
+    e = (p - (s - bb)) + (c - bb)
+    step = (e != 0) & ((s.view(np.int64) & 1) == 0)
+    s = np.where(step, np.nextafter(s, np.where(e > 0, np.inf, -np.inf)), s)
+    return s.astype(np.float32)
 SQ2PI = math.sqrt(2.0 / math.pi)
 SIGMA_GLOBAL = 0
 SIGMA_PER_CELL = 1
@@ -217,7 +237,7 @@ def decode(st: State):
     t = decode_table(st.nnu)
     half = (vel_m(st.nnu) - 1) // 2
     tv = t[st.nu.astype(np.int64) + half]
-    v = st.vc[:, cid] + st.vs[cid][None, :] * tv
+    v = fma32(st.vs[cid][None, :], tv, st.vc[:, cid])
     return l, v, cid
 
 
@@ -312,12 +332,12 @@ def move(st: State, phi32: np.ndarray, kfac32, dfac32, sigma_mode: int = SIGMA_P
             for cy in (0, 1):
                 d0 = dgrad(d, i0[0], i0[1] + cy, i0[2] + cz)
                 d1 = dgrad(d, i0[0] + 1, i0[1] + cy, i0[2] + cz)
-                r.append(w[0][0] * d0 + w[0][1] * d1)
-            s.append(w[1][0] * r[0] + w[1][1] * r[1])
-        t = w[2][0] * s[0] + w[2][1] * s[1]
+                r.append(fma32(w[0][1], d1, w[0][0] * d0))
+            s.append(fma32(w[1][1], r[1], w[1][0] * r[0]))
+        t = fma32(w[2][1], s[1], w[2][0] * s[0])
         tgrad[d] = t
-        vnew[d] = v[d] + t * kf
-    lnew = l + vnew * df
+        vnew[d] = fma32(t, kf, v[d])
+    lnew = fma32(vnew, df, l)
     cfl = bool(np.any(~np.isfinite(lnew)) or np.any(lnew < F32(-4)) or np.any(lnew >= F32(8)))
     k = np.where(lnew < F32(0), -1, np.where(lnew >= F32(4), 1, 0)).astype(np.int64)
     lw = np.where(k == 1, lnew - F32(4), np.where(k == -1, lnew + F32(4), lnew)).astype(np.float32)

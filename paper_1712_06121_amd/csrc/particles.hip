@@ -13,9 +13,10 @@
 // is handled by the workgroup that owns its coarse cell; the potential tile with a 3-cell halo
 // sits in LDS for the 4-point gradient.
 //
-// The arithmetic follows one fixed sequence of IEEE operations (no FMA contraction: this file is
-// compiled with -ffp-contract=off) so that the encoding, cell counts and order are reproducible
-// bit for bit from identical inputs.
+// The arithmetic follows one fixed sequence of IEEE operations so that the encoding, cell counts
+// and order are reproducible bit for bit from identical inputs: the compiler forms no fused
+// multiply-adds of its own (-ffp-contract=off), and the fused ones the sequence names -- velocity
+// decode, the interpolation lerps, kick and drift -- are written out as fmaf.
 #include <cstring>
 #include <type_traits>
 
@@ -548,7 +549,7 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
       l[d] = (float)(2 * ch[d] + 1) * unit;
       int nuv = (int)nu[d * a.cap + p];
       nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
-      v[d] = a.vc[d * a.nc3 + c] + a.vs[c] * a.tdec[nuv + a.vhalf];
+      v[d] = __builtin_fmaf(a.vs[c], a.tdec[nuv + a.vhalf], a.vc[d * a.nc3 + c]);
     }
     if constexpr (MODE == 0) {
       // CIC corners (fine cells relative to the tile origin) and exact dyadic weights
@@ -573,18 +574,18 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
           for (int cy = 0; cy < 2; ++cy) {
             const float d0 = grad_at<PRE>(ph, gd, d, i0[0], i0[1] + cy, i0[2] + cz);
             const float d1 = grad_at<PRE>(ph, gd, d, i0[0] + 1, i0[1] + cy, i0[2] + cz);
-            racc[cy] = w0[0] * d0 + w1[0] * d1;
+            racc[cy] = __builtin_fmaf(w1[0], d1, w0[0] * d0);
           }
-          sacc[cz] = w0[1] * racc[0] + w1[1] * racc[1];
+          sacc[cz] = __builtin_fmaf(w1[1], racc[1], w0[1] * racc[0]);
         }
-        const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
-        v[d] = v[d] + t * a.kf;
+        const float t = __builtin_fmaf(w1[2], sacc[1], w0[2] * sacc[0]);
+        v[d] = __builtin_fmaf(t, a.kf, v[d]);
         if constexpr (MEAS) m.tq = d == 0 ? t * t : m.tq + t * t;
       }
       if constexpr (MEAS) m.vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
+    for (int d = 0; d < 3; ++d) l[d] = __builtin_fmaf(v[d], a.df, l[d]);
   }
   m.ok = true;
 #pragma unroll
@@ -1051,7 +1052,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           int nuv = nuc[d];
           nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
           l[d] = (float)(2 * ch[d] + 1) * unit;
-          v[d] = vcv[d] + cv.w * tdec[nuv + a.vhalf];
+          v[d] = __builtin_fmaf(cv.w, tdec[nuv + a.vhalf], vcv[d]);
         }
         // CIC corners relative to the tile, exact dyadic weights, interpolated gradient
         const int o[3] = {ci, o1, o2};
@@ -1075,17 +1076,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
             for (int cy = 0; cy < 2; ++cy) {
               const float d0 = grad_at<true>(ph, gd, d, i0[0], i0[1] + cy, i0[2] + cz);
               const float d1 = grad_at<true>(ph, gd, d, i0[0] + 1, i0[1] + cy, i0[2] + cz);
-              racc[cy] = w0[0] * d0 + w1[0] * d1;
+              racc[cy] = __builtin_fmaf(w1[0], d1, w0[0] * d0);
             }
-            sacc[cz] = w0[1] * racc[0] + w1[1] * racc[1];
+            sacc[cz] = __builtin_fmaf(w1[1], racc[1], w0[1] * racc[0]);
           }
-          const float t = w0[2] * sacc[0] + w1[2] * sacc[1];
-          v[d] = v[d] + t * a.kf;
+          const float t = __builtin_fmaf(w1[2], sacc[1], w0[2] * sacc[0]);
+          v[d] = __builtin_fmaf(t, a.kf, v[d]);
           if constexpr (MEAS) tq = d == 0 ? t * t : tq + t * t;
         }
         if constexpr (MEAS) vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) l[d] = l[d] + v[d] * a.df;
+        for (int d = 0; d < 3; ++d) l[d] = __builtin_fmaf(v[d], a.df, l[d]);
       }
       if constexpr (MEAS) raise_maxima(a.amax, vv, tq);
       // new cell, codes, flags (same rules as the generic path)
@@ -1761,7 +1762,7 @@ __global__ void k_state_speed(const void* nu, const uint64_t* off, const float* 
     for (int d = 0; d < 3; ++d) {
       int c = (int)nv[d * cap + i];
       c = c < -vhalf ? -vhalf : (c > vhalf ? vhalf : c);
-      v[d] = vc[d * nc3 + lo] + vs[lo] * tdec[c + vhalf];
+      v[d] = __builtin_fmaf(vs[lo], tdec[c + vhalf], vc[d * nc3 + lo]);
     }
     vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
   }

@@ -110,3 +110,27 @@ def test_move_order_is_stable_within_cells():
     # zero drift and zero kick leaves positions and order unchanged
     same = twin.move(st, phi, np.float32(0.0), np.float32(0.0))
     assert np.array_equal(same.chi, st.chi) and np.array_equal(same.cnt, st.cnt)
+
+
+def test_fma32_is_correctly_rounded():
+    """fma32 against the exact rational a*b + c rounded to the nearest FP32 (ties to even)."""
+    from fractions import Fraction
+    g = np.random.default_rng(12)
+    n = 4000
+    a = g.normal(size=n).astype(np.float32) * np.float32(2.0) ** g.integers(-20, 20, n).astype(np.float32)
+    b = g.normal(size=n).astype(np.float32) * np.float32(2.0) ** g.integers(-20, 20, n).astype(np.float32)
+    c = g.normal(size=n).astype(np.float32) * np.float32(2.0) ** g.integers(-30, 30, n).astype(np.float32)
+    c[: n // 4] = -(a[: n // 4].astype(np.float64) * b[: n // 4]).astype(np.float32)  # cancellation
+    got = twin.fma32(a, b, c)
+
+    def round_f32(x: Fraction) -> np.float32:
+        f = np.float32(float(x))  # within one ulp; pick the nearest of the neighbours exactly
+        cands = [np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))]
+        best = min(cands, key=lambda y: (abs(Fraction(float(y)) - x), int(np.float32(y).view(np.int32)) & 1))
+        return best
+
+    for i in range(n):
+        exact = Fraction(float(a[i])) * Fraction(float(b[i])) + Fraction(float(c[i]))
+        assert got[i] == round_f32(exact), (a[i], b[i], c[i])
+    # the plain product is the special case c = 0
+    assert np.array_equal(twin.fma32(a, b, np.zeros(n, np.float32)), (a * b).astype(np.float32))
