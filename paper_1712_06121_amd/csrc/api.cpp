@@ -75,6 +75,10 @@ void build_tables(Sim& s) {
                                            [](double a, float e) { return a < (double)e; }) - s.h_tedge.begin());
     lo[b] = (int16_t)(cnt - half);
   }
+  // the move kernels rely on at most one edge per bucket (two exact steps then finish the search):
+  // consecutive lower-end codes differ by at most one
+  for (int b = 1; b < s.nbucket; ++b)
+    if (lo[b] - lo[b - 1] > 1) throw Error{CUBE_E_INVALID, "velocity bucket table holds two edges in one bucket"};
   s.tbucket = static_cast<int16_t*>(s.dmalloc(sizeof(int16_t) * s.nbucket));
   CUBE_HIP(hipMemcpy(s.tbucket, lo.data(), sizeof(int16_t) * s.nbucket, hipMemcpyHostToDevice));
   s.tdec = static_cast<float*>(s.dmalloc(sizeof(float) * m));

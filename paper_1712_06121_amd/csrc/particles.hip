@@ -808,11 +808,13 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // Eq. (nu) by the edge table: the code nu with ext[nu + h] <= u < ext[nu + h + 1] (h = (M-1)/2;
 // ext is the edge table with -inf and +inf at its ends), i.e. -h + #{edges <= u}. A bucket table
-// over t = u / (1 + |u|) gives the code at the lower end of the bucket, within two codes of the
-// answer (each bucket holds at most one edge, and an approximate t can miss its bucket by one);
-// two exact steps reach it, and the loops behind them (normally not entered) make the result exact
-// whatever the start.
-template <typename BT>
+// over t = u / (1 + |u|) gives the code at the lower end of the bucket. Every bucket holds at most
+// one edge (checked when the tables are built) and t, from an approximate reciprocal, is off by
+// far less than a bucket width, so the bucket found is the right one or a neighbour and the start
+// is within two codes of the answer; each exact step moves one code towards it, so two steps
+// reach it. With CHECKED, loops behind them (then never entered) keep the result exact whatever
+// the start. The sentinels keep every read inside the table, NaN included.
+template <bool CHECKED, typename BT>
 __device__ __forceinline__ int encode_nu(float u, const float* ext, const BT* bucket, int nbucket, int vhalf) {
   const float t = u * __builtin_amdgcn_rcpf(1.0f + fabsf(u));
   int b = (int)((t + 1.0f) * (0.5f * (float)nbucket));
@@ -820,8 +822,10 @@ __device__ __forceinline__ int encode_nu(float u, const float* ext, const BT* bu
   int nu = bucket[b];
 #pragma unroll
   for (int r = 0; r < 2; ++r) nu += (int)(u >= ext[nu + vhalf + 1]) - (int)(u < ext[nu + vhalf]);
-  while (u >= ext[nu + vhalf + 1]) ++nu;
-  while (u < ext[nu + vhalf]) --nu;
+  if constexpr (CHECKED) {
+    while (u >= ext[nu + vhalf + 1]) ++nu;
+    while (u < ext[nu + vhalf]) --nu;
+  }
   return nu;
 }
 
@@ -897,7 +901,7 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           const float u = (m.v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
-          nu_n[d * a.cap + dst] = (NT)encode_nu(u, edges, bucket, a.nbucket, a.vhalf);
+          nu_n[d * a.cap + dst] = (NT)encode_nu<false>(u, edges, bucket, a.nbucket, a.vhalf);
           chi_n[d * a.cap + dst] = (CT)m.chi[d];
         }
         if (a.pid_bytes) store_id(a, dst, particle_id<MODE>(a, g, s, (int64_t)start[s] + (i - pre[s]), i - pre[s]));
@@ -1198,7 +1202,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
               const float u = (v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
-              nu_n[d * a.cap + dst] = (NT)encode_nu(u, edges, bucket, a.nbucket, a.vhalf);
+              nu_n[d * a.cap + dst] = (NT)encode_nu<false>(u, edges, bucket, a.nbucket, a.vhalf);
               chi_n[d * a.cap + dst] = (CT)cq[d];
             }
             if (a.pid_bytes) store_id(a, dst, particle_id<0>(a, g, s, (int64_t)(base + j), 0u));
@@ -1455,7 +1459,7 @@ __global__ void k_load_encode(const uint32_t* key_sorted, const uint32_t* idx_so
   for (int d = 0; d < 3; ++d) {
     co[d * cap + j] = (CT)chi_tmp[d * n + src];
     const float u = (v_tmp[d * n + src] - vc[d * nc3 + c]) * inv;
-    no[d * cap + j] = (NT)encode_nu(u, edges, bucket, nbucket, vhalf);
+    no[d * cap + j] = (NT)encode_nu<true>(u, edges, bucket, nbucket, vhalf);
   }
   // the ID of a loaded particle is its index in the input
   if (pid_bytes == 8) static_cast<uint64_t*>(pid_out)[j] = (uint64_t)src;
