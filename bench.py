@@ -293,7 +293,7 @@ def main() -> int:
     ap.add_argument("--serve-slice", type=int, default=5)
     ap.add_argument("--serve-budget-gb", type=int, default=160)
     ap.add_argument("--cpu-sample-side", type=int, default=128)
-    ap.add_argument("--cpu-sample-steps", type=int, default=5)
+    ap.add_argument("--cpu-sample-steps", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants instead of timing the equivalent ones after warm-up")
