@@ -189,6 +189,7 @@ int enqueue_adaptive(Sim& s, int k) {
     launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream, nullptr);
     double vm = 0.0, gm = 0.0;
     read_maxima(s, &vm, &gm);
+    check_flags(s);  // the step has been waited for anyway: stop at a failed step, not after k
     s.meas_v.push_back(vm);
     s.meas_g.push_back(gm);
     const double an = s.a_int[j + 2];
