@@ -436,6 +436,7 @@ def main() -> int:
             "frac": step_bytes / k_step / 1e9 / HBM_PEAK_GBS,
         },
         "kernels_ms": ms,
+        "kernels_algorithmic_GBs": {k: ab[k] / (ms[k] * 1e-3) / 1e9 for k in KERNELS if ms[k] > 0},
         "kernels_sum_ms": step_ms,
         "cpu_baseline": cpu,
     }
