@@ -418,11 +418,12 @@ __device__ __forceinline__ void resolve_factors(MoveArgs& a) {
   }
 }
 
-// rint(x) as int64 for |x| < 2^51: adding 1.5 * 2^52 rounds x to the nearest integer (ties to
-// even, as rint does) in the low mantissa bits; the difference of the bit patterns is that integer
-__device__ __forceinline__ long long rint_ll(double x) {
+// rint(x s) as int64 for a power of two s and |x s| < 2^51: adding 1.5 * 2^52 rounds x s to the
+// nearest integer (ties to even, as rint does) in the low mantissa bits; the difference of the bit
+// patterns is that integer. x s is exact, so the fused multiply-add rounds once, as the sum would.
+__device__ __forceinline__ long long rint_ll(double x, double s) {
   const double magic = 6755399441055744.0;
-  return __double_as_longlong(x + magic) - __double_as_longlong(magic);
+  return __double_as_longlong(__builtin_fma(x, s, magic)) - __double_as_longlong(magic);
 }
 
 // fixed-point velocity moments of one particle: rint(v_d 2^32) and sum_d rint(v_d^2 2^24). The
@@ -435,14 +436,14 @@ __device__ __forceinline__ void velocity_moments(const float* v, long long* q) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double vd = (double)v[d];
-      q[d] = rint_ll(vd * 4294967296.0);
-      q[3] += rint_ll(vd * vd * 16777216.0);
+      q[d] = rint_ll(vd, 4294967296.0);
+      q[3] += rint_ll(vd * vd, 16777216.0);
     }
   } else {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double vd = (double)v[d];
-      q[d] = rint_ll(vd * 4294967296.0);
+      q[d] = rint_ll(vd, 4294967296.0);
       q[3] += __double2ll_rn(vd * vd * 16777216.0);
     }
   }
@@ -605,29 +606,57 @@ __device__ __forceinline__ Moved move_particle(const MoveArgs& a, const float* p
 template <int MODE, bool PRE, int NTH>
 __device__ __forceinline__ void load_potential(const MoveArgs& a, float* ph, float* gd, const TileGeom& g) {
   if constexpr (MODE == 0) {
-    // half-waves take rows (z, y); lanes take x
-    const int hw = threadIdx.x >> 5, x = threadIdx.x & 31;
     const int fx0 = g.cx0 * 4 - 3, fy0 = g.cy0 * 4 - 3, fz0 = g.cz0 * 4 - 3;
-    const int gx = wrapi(fx0 + x, a.nm);
+    const int64_t plane = (int64_t)a.nm * a.pitch_f;
     // all loads of the tile in flight at once, then into LDS
-    constexpr int NR = (PH * PH + NTH / 32 - 1) / (NTH / 32);
-    float stage[NR];
+    if (fx0 >= 0 && fy0 >= 0 && fz0 >= 0 && fx0 + PH <= a.nm && fy0 + PH <= a.nm && fz0 + PH <= a.nm &&
+        plane < (1 << 26)) {
+      // the halo does not cross the box boundary: element e of the tile lies at a 32-bit offset
+      // from the tile's first element (below 22 planes of fewer than 2^26 floats); its row index
+      // z nm + y and the row pitch are below 2^24, so 24-bit multiplies form the offset
+      const float* src = a.mesh + (int64_t)fz0 * plane + (int64_t)fy0 * a.pitch_f + fx0;
+      const uint32_t nmu = (uint32_t)a.nm, rs = (uint32_t)a.pitch_f;
+      constexpr int NE = PH * PH * PH;
+      constexpr int NL = (NE + NTH - 1) / NTH;
+      float stage[NL];
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int r = hw + k * (NTH / 32);
-      if (x < PH && r < PH * PH) {
-        const int z = r / PH, y = r - z * PH;
-        const int gy = wrapi(fy0 + y, a.nm), gz = wrapi(fz0 + z, a.nm);
-        stage[k] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
+      for (int k = 0; k < NL; ++k) {
+        const uint32_t e = threadIdx.x + k * NTH;
+        if (NE % NTH == 0 || e < (uint32_t)NE) {
+          const uint32_t q = e / PH, x = e - q * PH;
+          const uint32_t z = q / PH, y = q - z * PH;
+          stage[k] = src[__umul24(__umul24(z, nmu) + y, rs) + x];
+        }
       }
-    }
 #pragma unroll
-    for (int k = 0; k < NR; ++k) {
-      const int r = hw + k * (NTH / 32);
-      if (x < PH && r < PH * PH) ph[r * PH + x] = stage[k];
+      for (int k = 0; k < NL; ++k) {
+        const uint32_t e = threadIdx.x + k * NTH;
+        if (NE % NTH == 0 || e < (uint32_t)NE) ph[e] = stage[k];
+      }
+    } else {
+      // half-waves take rows (z, y), wrapped periodically; lanes take x
+      const int hw = threadIdx.x >> 5, x = threadIdx.x & 31;
+      const int gx = wrapi(fx0 + x, a.nm);
+      constexpr int NR = (PH * PH + NTH / 32 - 1) / (NTH / 32);
+      float stage[NR];
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int r = hw + k * (NTH / 32);
+        if (x < PH && r < PH * PH) {
+          const int z = r / PH, y = r - z * PH;
+          const int gy = wrapi(fy0 + y, a.nm), gz = wrapi(fz0 + z, a.nm);
+          stage[k] = a.mesh[((int64_t)gz * a.nm + gy) * a.pitch_f + gx];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NR; ++k) {
+        const int r = hw + k * (NTH / 32);
+        if (x < PH && r < PH * PH) ph[r * PH + x] = stage[k];
+      }
     }
     if constexpr (PRE) {
       __syncthreads();
+      const int hw = threadIdx.x >> 5, x = threadIdx.x & 31;
       for (int r = hw; r < DG * DG; r += NTH / 32) {
         if (x < DG) {
           const int z = r / DG, y = r - z * DG;
@@ -682,6 +711,17 @@ __device__ __forceinline__ int find_cell_in(const uint32_t* pre, int lo, int hi,
     else hi = mid;
   }
   return lo;
+}
+
+// The tile's per (own cell, displacement) counts (LDS, [cell][27]) to mig[d][cell]: a wavefront
+// writes one displacement of all 64 own cells, a lane per cell, so the array offset is uniform.
+template <int NTH>
+__device__ __forceinline__ void flush_counts(const MoveArgs& a, const TileGeom& g, const uint32_t* cnt) {
+  static_assert(TC == 64 && NTH % 64 == 0, "one lane per own cell");
+  const int s = threadIdx.x & 63;
+  uint32_t* const col = a.mig + (g.cx0 + (int64_t)a.nc * (g.cy0 + (int64_t)a.nc * g.cz0)) + s % T +
+                        (int64_t)a.nc * ((s / T) % T) + (int64_t)a.nc * a.nc * (s / (T * T));
+  for (int d = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); d < 27; d += NTH / 64) col[d * a.nc3] = cnt[s * 27 + d];
 }
 
 template <int MODE, bool PRE>
@@ -780,11 +820,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < TC * 27; i += NTH) {
-    const int s = i / 27, d = i % 27;
-    const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
-    a.mig[d * a.nc3 + c] = mcnt[i];
-  }
+  flush_counts<NTH>(a, g, mcnt);
   if constexpr (L::kGlobalMom) {
     for (int i = threadIdx.x; i < TC * 4; i += NTH) {
       const unsigned long long v = mom[i];
@@ -942,7 +978,44 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   __shared__ float edges_lds[(SCATTER && NNU == 1) ? 256 : 1];
   __shared__ int8_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];  // 1-byte codes fit int8
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
-  load_potential<0, false, NTH>(a, ph, nullptr, g);
+  // mean velocity and decode scale of the tile's cells
+  __shared__ float4 cellv[TC];
+  uint32_t cnt_r = 0;  // particle count of own cell threadIdx.x
+  {
+    // every global read of the set-up in flight at once: the code tables, the own cells' counts,
+    // starts, mean velocities and decode scales, then the potential tile
+    static_assert(NTH >= 1024 && NTH >= TC, "one table entry and at most one own cell per thread");
+    float tdec_r = 0.0f, edge_r = 0.0f;
+    int bucket_r = 0;
+    if constexpr (NNU == 1) {
+      if (threadIdx.x < 255) tdec_r = a.tdec[threadIdx.x];
+      if constexpr (SCATTER) {
+        if (threadIdx.x < 256) edge_r = a.tedge[threadIdx.x];
+        if ((int)threadIdx.x < a.nbucket) bucket_r = a.tbucket[threadIdx.x];
+      }
+    }
+    float4 cv_r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    uint64_t start_r = 0;
+    if (threadIdx.x < TC) {
+      const int sx = threadIdx.x;
+      const int64_t c = (g.cx0 + sx % T) + (int64_t)a.nc * ((g.cy0 + (sx / T) % T) + (int64_t)a.nc * (g.cz0 + sx / (T * T)));
+      cnt_r = a.cnt[c];
+      start_r = a.off[c];
+      cv_r = make_float4(a.vc[c], a.vc[a.nc3 + c], a.vc[2 * a.nc3 + c], a.vs[c]);
+    }
+    load_potential<0, false, NTH>(a, ph, nullptr, g);
+    if constexpr (NNU == 1) {
+      if (threadIdx.x < 255) tdec_lds[threadIdx.x] = tdec_r;
+      if constexpr (SCATTER) {
+        if (threadIdx.x < 256) edges_lds[threadIdx.x] = edge_r;
+        if ((int)threadIdx.x < a.nbucket) bucket_lds[threadIdx.x] = (int8_t)bucket_r;
+      }
+    }
+    if (threadIdx.x < TC) {
+      cellv[threadIdx.x] = cv_r;
+      start[threadIdx.x] = start_r;
+    }
+  }
   __syncthreads();
   {
     // gradient of every corner cell -1 .. F of the tile, over the potential: the z component lies
@@ -979,13 +1052,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     }
   }
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
-  if constexpr (NNU == 1) {
-    for (int i = threadIdx.x; i < 255; i += NTH) tdec_lds[i] = a.tdec[i];
-    if constexpr (SCATTER) {
-      for (int i = threadIdx.x; i < 256; i += NTH) edges_lds[i] = a.tedge[i];
-      for (int i = threadIdx.x; i < a.nbucket; i += NTH) bucket_lds[i] = (int8_t)a.tbucket[i];
-    }
-  }
   const float* tdec = NNU == 1 ? tdec_lds : a.tdec;
   const float* edges = NNU == 1 ? edges_lds : a.tedge;
   using BT = std::conditional_t<NNU == 1, int8_t, int16_t>;
@@ -996,14 +1062,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   __shared__ unsigned long long omom[SCATTER ? 1 : TC * 4];
   if constexpr (!SCATTER)
     for (int i = threadIdx.x; i < TC * 4; i += NTH) omom[i] = 0ull;
-  // mean velocity and decode scale of the tile's cells
-  __shared__ float4 cellv[TC];
-  if (threadIdx.x < TC) {
-    const int sx = threadIdx.x;
-    const int64_t c = (g.cx0 + sx % T) + (int64_t)a.nc * ((g.cy0 + (sx / T) % T) + (int64_t)a.nc * (g.cz0 + sx / (T * T)));
-    cellv[sx] = make_float4(a.vc[c], a.vc[a.nc3 + c], a.vc[2 * a.nc3 + c], a.vs[c]);
-  }
-  own_cells<0>(a, g, pre, start, wsum);  // ends with a barrier
+  block_exclusive_scan(cnt_r, pre, TC, wsum);  // ends with a barrier
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const unsigned long long lt = (1ull << lane) - 1ull;
@@ -1215,11 +1274,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   }
   if constexpr (!SCATTER) {
     __syncthreads();
-    for (int i = threadIdx.x; i < TC * 27; i += NTH) {
-      const int s = i / 27, d = i % 27;
-      const int64_t c = (g.cx0 + s % T) + (int64_t)a.nc * ((g.cy0 + (s / T) % T) + (int64_t)a.nc * (g.cz0 + s / (T * T)));
-      a.mig[d * a.nc3 + c] = grp[i];
-    }
+    flush_counts<NTH>(a, g, grp);
     if (threadIdx.x < TC * 4) {
       const int so = threadIdx.x / 4, d = threadIdx.x % 4;
       const unsigned long long m = omom[threadIdx.x];
