@@ -249,15 +249,24 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
     __syncthreads();
     auto deposit_layer = [&](auto* acc) {
     using A = typename std::remove_pointer<decltype(acc)>::type;
-    for (uint32_t it = threadIdx.x; it < total; it += BLK) {
+    // source cell and codes of the layer's it-th particle
+    auto fetch = [&](uint32_t it, int& s, int* ch) {
       // interleaved: lane l of the w-th group of 64 takes particle l * (total / 64) + w, so the lanes
       // of one wavefront hold particles of different cells (a bijection on [0, 64 * (total / 64)))
       const uint32_t i = (a.interleave && it < 64 * q64) ? (it % 64) * q64 + it / 64 : it;
-      int s = owner[i >> osh];
+      s = owner[i >> osh];
       while (pre[s + 1] <= i) ++s;
       const int64_t p = (int64_t)start[s] + (i - pre[s]);
+      ch[0] = (int)cx[p];
+      ch[1] = (int)cy[p];
+      ch[2] = (int)cz[p];
+    };
+    // CIC of one particle with source cell s and codes ch
+    auto deposit_one = [&](const int s, const int* ch) {
+      // the three codes are needed here on every path: without this the compiler may move their
+      // uses into the conditional corners and then wait conservatively for later loads as well
+      asm volatile("" ::"v"(ch[0]), "v"(ch[1]), "v"(ch[2]));
       const int sl[3] = {s % DR - 1, s / DR - 1, sz};
-      const int ch[3] = {(int)cx[p], (int)cy[p], (int)cz[p]};
       int i0[3], w1[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -287,6 +296,23 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
             atomicAdd(&acc[sb + y * DF + x], w);
           }
         }
+      }
+    };
+    // software pipeline, unrolled twice so that the two particles' registers alternate: a thread
+    // requests the codes of its next particle before it computes the weights and issues the LDS
+    // atomics of the current one, so the global-memory latency overlaps them. The requests are
+    // unconditional (past the end they repeat the layer's last particle, whose codes go unused) so
+    // that the wait for the current codes never waits for the next ones.
+    if (total > 0) {
+      const uint32_t last = total - 1;
+      int s0, s1, ch0[3], ch1[3];
+      fetch(min((uint32_t)threadIdx.x, last), s0, ch0);
+      for (uint32_t it = threadIdx.x; it < total; it += 2 * BLK) {
+        fetch(min(it + BLK, last), s1, ch1);
+        deposit_one(s0, ch0);
+        if (it + BLK >= total) break;
+        fetch(min(it + 2 * BLK, last), s0, ch0);
+        deposit_one(s1, ch1);
       }
     }
     };
