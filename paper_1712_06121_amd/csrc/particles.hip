@@ -1110,17 +1110,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const int64_t crow = (int64_t)a.nc * ((g.cy0 + o1) + (int64_t)a.nc * (g.cz0 + o2));
     // the codes of the next chunk are loaded before this chunk's atomics and stores are issued, so
     // waiting for them never waits for those (the vector memory counter is in order)
+    // unconditional loads (past the row's end they repeat its last particle, whose codes go
+    // unused), so that the number of memory operations issued after them does not depend on the
+    // path and the wait for them does not also wait for this chunk's stores and atomics
     int chn[3] = {0, 0, 0}, nun[3] = {0, 0, 0};
     auto load_chunk = [&](uint32_t jj) {
-      if (jj < nrow) {
+      jj = min(jj, nrow - 1);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          chn[d] = (int)chx[d * a.cap + jj];
-          nun[d] = (int)nux[d * a.cap + jj];
-        }
+      for (int d = 0; d < 3; ++d) {
+        chn[d] = (int)chx[d * a.cap + jj];
+        nun[d] = (int)nux[d * a.cap + jj];
       }
     };
-    load_chunk(lane);
+    if (nrow > 0) load_chunk(lane);
     uint32_t scnt[T] = {0u, 0u, 0u, 0u};  // scatter: stayers ranked so far per cell of the row
     for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
       const uint32_t j = j0 + lane;
@@ -1128,7 +1130,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const int ci = (int)(j >= p1) + (int)(j >= p2) + (int)(j >= p3);  // cell of the row
       const int s = s0 + ci;
       const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
-      if (j0 + 64 < nrow) load_chunk(j + 64);
+      load_chunk(j + 64);
       float v[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
       float vv = 0.f, tq = 0.f;
       int ch[3] = {0, 0, 0};
