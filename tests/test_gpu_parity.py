@@ -77,6 +77,21 @@ def test_deposit_bit_exact(Sim, nchi, nm, clumps):
     assert np.array_equal(got, exp)
 
 
+@pytest.mark.parametrize("n", [1, 37, 900])
+def test_deposit_sparse_bit_exact(Sim, n):
+    # layers with no particle at all and layers with fewer particles than a workgroup has threads
+    # (the deposit's software pipeline clamps its look-ahead to the layer's last particle)
+    nm = 64
+    x, v = synth.particle_cloud(77 + n, n, nm, clump_frac=0.0)
+    ref = twin.load(x, v, nm // 4, 1, 1)
+    with Sim(np_for(nm), nm, 100.0, capacity=n) as sim:
+        sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
+        sim.stage_deposit()
+        got = sim.get_mesh()
+    exp = twin.delta_from_rho(twin.deposit_int(ref, nm), ref.n, 1)
+    assert np.array_equal(got, exp)
+
+
 @pytest.mark.parametrize("nm", [32, 64, 96, 192, 256])
 def test_solve_within_tolerance(Sim, nm):
     nc = nm // 4
