@@ -5,10 +5,13 @@
 
 One step = the whole hot path on the resident compressed state: integer CIC deposit, five-pass
 FFT Poisson solve, force interpolation + kick + drift + re-encode (count pass, per-cell link and
-scan, scatter pass). Initial conditions are generated on the GPU before the timed region.
-Prints one JSON line: particle-steps/s, the roofline of the dominant kernel (algorithmic bytes
-per launch over its HIP-event-timed duration, against the 8 TB/s HBM peak) and the oracle timed
-on the host cores on a bounded sample of the same workload.
+scan, scatter pass). Initial conditions are generated on the GPU before the timed region. After W
+warm-up steps (and the variant autotuner) the K steps right after them are timed as an early
+window when the schedule leaves room, the run continues untimed, and the LAST K steps of the
+schedule, ending at a = 1 where the particles are most clustered, are the timed region of `value`.
+Prints one JSON line: particle-steps/s, the HBM roofline of the dominant kernel (algorithmic bytes
+per launch over its HIP-event-timed duration, against the 8 TB/s peak; its vector-ALU view beside
+it) and the oracle timed on the host cores on bounded samples of the workloads.
 """
 from __future__ import annotations
 
@@ -95,35 +98,60 @@ def measured_valu(kernel: str):
     return None
 
 
-def cpu_baseline(cfg: dict, sample_side: int, steps: int):
-    """The oracle (plain FP64 numpy PM on uncompressed particles) on a sub-box with the workload's
-    particle and mesh resolution; particle-steps per second of host time."""
-    import numpy as np
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(steps: dict):
+    """The oracle (plain FP64 numpy PM on uncompressed particles, oracle.pm) timed on the host:
+    the Poisson solve through scipy.fft with every host thread, CIC deposit and interpolation with
+    numpy (one thread). Workloads: C1 (32^3 particles, 64^3 mesh), C2 (128^3, 256^3) and the 256^3
+    sibling of the 2048^3 workload (same particle and mesh resolution), each from its own
+    Zel'dovich initial conditions (untimed), `steps[name]` DKD steps timed after the initial half
+    drift. `value` is the sibling's particle-steps/s: the rate at the headline workload's
+    resolution."""
     from oracle import ic, pm
     from oracle.cosmology import Cosmology
 
-    ratio = cfg["nm_side"] // cfg["np_side"]
-    nm = sample_side * ratio
-    box = cfg["box"] * sample_side / cfg["np_side"]
-    cosmo = Cosmology(cfg["omega_m"], cfg["omega_l"], h=cfg["h"], sigma8=cfg["sigma8"], n_s=cfg["n_s"])
-    x, p, _ = ic.zeldovich(sample_side, nm, box, cosmo, cfg["a_init"], cfg["seed"])
-    run = pm.PMRun(x, p, nm, cosmo, cfg["a_init"], cfg["a_final"], cfg["n_steps"], cfg.get("spacing", 0))
-    run.advance()  # initial half drift, untimed
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        run.advance()
-    dt = time.perf_counter() - t0
-    n = sample_side**3
+    threads = os.cpu_count() or 1
+    pm.FFT_WORKERS = threads
+    per = {}
+    try:
+        for name, k in steps.items():
+            cfg = synth.WORKLOADS[name]
+            cosmo = Cosmology(cfg["omega_m"], cfg["omega_l"], h=cfg["h"], sigma8=cfg["sigma8"], n_s=cfg["n_s"])
+            x, p, _ = ic.zeldovich(cfg["np_side"], cfg["nm_side"], cfg["box"], cosmo, cfg["a_init"], cfg["seed"])
+            run = pm.PMRun(x, p, cfg["nm_side"], cosmo, cfg["a_init"], cfg["a_final"], cfg["n_steps"],
+                           cfg.get("spacing", 0))
+            run.advance()  # initial half drift, untimed
+            t0 = time.perf_counter()
+            for _ in range(k):
+                run.advance()
+            dt = time.perf_counter() - t0
+            n = cfg["np_side"] ** 3
+            per[name] = {"steps": k, "seconds": dt, "ms_per_step": 1e3 * dt / k, "particle_steps_per_s": n * k / dt}
+            print(f"[bench] oracle {name}: {k} steps in {dt:.1f} s", file=sys.stderr, flush=True)
+    finally:
+        pm.FFT_WORKERS = None
+    sib = per["c3_sibling256"]
     return {
-        "value": n * steps / dt,
+        "value": sib["particle_steps_per_s"],
         "unit": "particle-steps/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"{steps} DKD steps of the FP64 numpy oracle on a {sample_side}^3-particle, {nm}^3-mesh "
-                  f"sub-box ({box:g} Mpc/h, same particle and mesh resolution as the workload); "
-                  f"{dt:.1f} s on 1 host thread (numpy FFT and bincount are single-threaded)",
-        "seconds": dt,
-        "host_cpus": os.cpu_count(),
+        "sample": f"FP64 numpy oracle (oracle.pm.PMRun, uncompressed particles): {sib['steps']} DKD steps of the "
+                  f"256^3-particle, 256^3-mesh, 250 Mpc/h sibling of the 2048^3 workload (same particle and mesh "
+                  f"resolution) in {sib['seconds']:.1f} s; scipy.fft with {threads} threads for the Poisson "
+                  f"solve, numpy CIC deposit and interpolation on one thread",
+        "cpu_model": host_cpu_model(),
+        "host_cpus": threads,
+        "workloads": per,
     }
 
 
@@ -292,8 +320,10 @@ def main() -> int:
     ap.add_argument("--serve-slots", type=int, default=24)
     ap.add_argument("--serve-slice", type=int, default=5)
     ap.add_argument("--serve-budget-gb", type=int, default=160)
-    ap.add_argument("--cpu-sample-side", type=int, default=128)
-    ap.add_argument("--cpu-sample-steps", type=int, default=15)
+    ap.add_argument("--cpu-c1-steps", type=int, default=50, help="oracle steps timed on C1 (32^3 particles)")
+    ap.add_argument("--cpu-c2-steps", type=int, default=4, help="oracle steps timed on C2 (128^3 particles)")
+    ap.add_argument("--cpu-sibling-steps", type=int, default=2,
+                    help="oracle steps timed on the 256^3 sibling of the 2048^3 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants instead of timing the equivalent ones after warm-up")
@@ -345,15 +375,40 @@ def main() -> int:
         torch.cuda.synchronize()
         print(f"[bench] autotune in {time.perf_counter() - t0:.1f} s: {sim.variant}", file=sys.stderr, flush=True)
 
-    sim.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms = dict(zip(KERNELS, (float(t) for t in sim.get_timings())))
-    sim.set_profiling(False)
-    print(f"[bench] {args.steps} timed steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    def timed_window(k):
+        """k steps with per-kernel HIP events; (wall seconds, kernel ms per step, scale factors)."""
+        a0 = sim.a
+        sim.set_profiling(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sim.step(k)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ms_k = dict(zip(KERNELS, (float(x) for x in sim.get_timings())))
+        sim.set_profiling(False)
+        return el, ms_k, (a0, sim.a)
+
+    # early window: the steps right after the warm-up (near-linear regime), when it does not overlap
+    # the late window; then untimed steps up to the late window: the last `steps` steps of the
+    # schedule, ending at a = 1 (the clustered regime), which give `value`
+    early = None
+    n_total = cfg["n_steps"]
+    if args.warmup + 2 * args.steps <= n_total:
+        el, ms_e, a_e = timed_window(args.steps)
+        early = {"steps": args.steps, "a": a_e, "ms_per_step": 1e3 * el / args.steps,
+                 "value": cfg["np_side"] ** 3 * args.steps / el, "kernels_ms": ms_e}
+        print(f"[bench] early window a={a_e[0]:.3f}..{a_e[1]:.3f}: {1e3 * el / args.steps:.1f} ms/step",
+              file=sys.stderr, flush=True)
+    skip = n_total - args.steps - sim.steps_done
+    while skip > 0:
+        k = min(skip, 10)
+        sim.step(k)
+        torch.cuda.synchronize()
+        skip -= k
+        print(f"[bench] untimed steps to {sim.steps_done} (a={sim.a:.3f})", file=sys.stderr, flush=True)
+    elapsed, ms, a_late = timed_window(args.steps)
+    print(f"[bench] late window a={a_late[0]:.3f}..{a_late[1]:.3f}: {args.steps} timed steps in {elapsed:.3f} s",
+          file=sys.stderr, flush=True)
 
     n = cfg["np_side"] ** 3
     value = n * args.steps / elapsed
@@ -361,7 +416,7 @@ def main() -> int:
     dom = max(KERNELS, key=lambda k: ms[k])
     achieved = ab[dom] / (ms[dom] * 1e-3) / 1e9
     full = args.workload == "c3_pm2048"
-    hbm_view = {
+    roofline = {
         "bound": "hbm",
         "kernel": dom,
         "achieved": achieved,
@@ -372,27 +427,24 @@ def main() -> int:
         "algorithmic_bytes_per_launch": ab[dom],
         "avg_launch_ms": ms[dom],
     }
+    roofline_alu = None
     if dom in ALGO_OPS_PER_PARTICLE:
-        # the move passes issue vector instructions back to back (about one per SIMD every 4 cycles):
-        # they are bound by the vector ALU, not by HBM
+        # the move passes issue vector instructions back to back: their other bound is the vector ALU
         ops = ALGO_OPS_PER_PARTICLE[dom] * cfg["np_side"] ** 3
         tops = ops / (ms[dom] * 1e-3) / 1e12
         valu = measured_valu(dom) if full else None
-        roofline = {
+        roofline_alu = {
             "bound": "alu",
             "kernel": dom,
             "achieved": tops,
             "peak": ALU_PEAK_TOPS,
             "unit": "TOP/s",
             "frac": tops / ALU_PEAK_TOPS,
-            "traffic": hbm_view["traffic"],
             "algorithmic_ops_per_launch": ops,
             "avg_launch_ms": ms[dom],
             "valu_instructions_per_launch": valu,
             "cycles_per_valu_issue_per_simd": (ms[dom] * 1e-3 * 2.4e9 / (valu / 1024)) if valu else None,
         }
-    else:
-        roofline = hbm_view
     step_bytes = sum(ab.values())
     step_ms = sum(ms.values())
     k_step = elapsed / args.steps
@@ -400,7 +452,8 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(cfg, args.cpu_sample_side, args.cpu_sample_steps)
+        cpu = cpu_baseline({"c1_pm32": args.cpu_c1_steps, "c2_pm128": args.cpu_c2_steps,
+                            "c3_sibling256": args.cpu_sibling_steps})
 
     out = {
         "metric": "particle-steps/s",
@@ -428,8 +481,10 @@ def main() -> int:
             "sigma": "per-cell",
             "variants": sim.variant,
         },
+        "window": {"steps": args.steps, "a": a_late, "position": "last steps of the schedule, ending at a_final"},
+        "early_window": early,
         "roofline": roofline,
-        "roofline_hbm": hbm_view,
+        "roofline_alu": roofline_alu,
         "step_roofline": {
             "algorithmic_bytes": step_bytes,
             "achieved_GBs": step_bytes / k_step / 1e9,

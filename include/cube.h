@@ -117,8 +117,19 @@ int cube_load_particles(cube_sim* sim, const double* x, const double* v, int64_t
 /* Advance k leapfrog steps (Fig. code): before the first step the initial half drift; each step
  * deposits, solves, kicks and drifts; the last step ends with the final half drift at a_final.
  * Returns CUBE_DONE when a_final has been reached (remaining steps are not taken).
- * Errors: CUBE_E_CFL, CUBE_E_NONFINITE, CUBE_E_OVERFLOW, CUBE_E_STATE. */
+ * The k steps are enqueued without waiting; the device error flags are read once at the end. A
+ * step whose move raises a flag is not applied, and neither is any later one: the call then
+ * returns the error with the state, cube_steps_done and cube_scale_factor those before the
+ * failing step (or before the initial half drift), and the error text names that step.
+ * Errors: CUBE_E_CFL, CUBE_E_NONFINITE, CUBE_E_OVERFLOW (a velocity of 2^15 fine cells x H0 or
+ * more, or a coarse cell whose n x 3-D velocity variance reaches 2^34), CUBE_E_STATE. */
 int cube_step(cube_sim* sim, int32_t k);
+
+/* Failure injection for tests of the error path: raise the device error bits `flag` (1 CFL,
+ * 2 non-finite, 4 overflow, 8 count) just before the move of step `step` of later cube_step or
+ * cube_batch_step calls, as if that move had raised them; step -1 switches it off.
+ * Errors: CUBE_E_INVALID. */
+int cube_debug_inject_flag(cube_sim* sim, int32_t step, uint32_t flag);
 
 /* Adaptive time steps (Sec. 2.3.3: the step is bounded by the particles' largest velocity and
  * acceleration and by the expansion), chosen before the first step; eta_v = eta_a = eta_e = 0
@@ -166,7 +177,7 @@ int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* 
  * has |n_i| < nm/2 of the smaller mesh (its Nyquist planes are aliased). Host outputs of length
  * nbins: mean |k|, P_aa, P_bb, P_ab and the number of modes. `a` and `b` may be the same
  * simulation; two simulations must be on one device (their streams are ordered by an event) and
- * have equal box sizes. Errors are reported on `a`: CUBE_E_INVALID, CUBE_E_STATE, CUBE_E_HIP.
+ * have equal box sizes. Errors are reported on `a`: CUBE_E_INVALID, CUBE_E_STATE, CUBE_E_DEVICE.
  * Overwrites both meshes (scratch between steps). */
 int cube_get_cross_power(cube_sim* a, cube_sim* b, int32_t nbins, double* k, double* paa, double* pbb,
                          double* pab, double* nmodes);
@@ -270,7 +281,9 @@ typedef struct {
                               per XCD */
   int32_t deposit_variant; /* bit 0: particles of a layer visited with a stride of 1/64 of the layer
                               (lanes of a wavefront in different cells); bit 1: 512-thread
-                              workgroups instead of 256; default 3 */
+                              workgroups instead of 256; bit 2: source cells in three groups
+                              (interior, other own, ring) with the ring particles that reach the
+                              column gathered into full wavefronts (bit 0 ignored); default 3 */
   int32_t fft_z_layout;    /* 0 (default): z pass in place on the mesh; 1: the forward y pass writes
                               a z-contiguous copy, the z pass works there and the inverse y pass
                               writes back (one more mesh-sized device buffer, allocated when chosen
@@ -319,7 +332,10 @@ int cube_batch_init_ic(cube_batch* b);
  * applied to every box of that shape. */
 int cube_batch_autotune(cube_batch* b);
 /* Advance every box k steps (one graph launch per step); the error flags of every box are
- * checked once at the end. Returns CUBE_DONE when the boxes have reached a_final. */
+ * checked once at the end. A box whose step fails stays at the state before that step, as in
+ * cube_step, while the other boxes keep their steps; the first failure is returned (its text
+ * names the box and the step) and the batch then refuses to step until the boxes are at one step
+ * again. Returns CUBE_DONE when the boxes have reached a_final. */
 int cube_batch_step(cube_batch* b, int32_t k);
 
 /* ---- serving: continuous batching of simulation jobs -----------------------------------------

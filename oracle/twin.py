@@ -47,6 +47,7 @@ exactly; the move agrees with an FP64 evaluation of the same formulas to FP32 ro
 """
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass
 
@@ -81,16 +82,22 @@ def vel_m(nnu: int) -> int:
     return (1 << (8 * nnu)) - 1
 
 
+@functools.lru_cache(maxsize=None)
 def decode_table(nnu: int) -> np.ndarray:
-    """T[nu + (M-1)/2] = FP32(tan(pi nu / M)), computed with the C library tan in FP64."""
+    """T[nu + (M-1)/2] = FP32(tan(pi nu / M)), computed with the C library tan in FP64 (read-only,
+    computed once per code width)."""
     m = vel_m(nnu)
     half = (m - 1) // 2
-    return np.array([math.tan(math.pi * float(nu) / float(m)) for nu in range(-half, half + 1)],
-                    dtype=np.float64).astype(np.float32)
+    t = np.array([math.tan(math.pi * float(nu) / float(m)) for nu in range(-half, half + 1)],
+                 dtype=np.float64).astype(np.float32)
+    t.flags.writeable = False
+    return t
 
 
+@functools.lru_cache(maxsize=None)
 def edge_table(nnu: int) -> np.ndarray:
-    """Bin edges of Eq. (nu) rounded up to FP32 (M - 1 entries, ascending)."""
+    """Bin edges of Eq. (nu) rounded up to FP32 (M - 1 entries, ascending; read-only, computed once
+    per code width)."""
     m = vel_m(nnu)
     half = (m - 1) // 2
     out = np.empty(m - 1, dtype=np.float32)
@@ -100,6 +107,7 @@ def edge_table(nnu: int) -> np.ndarray:
         if float(f) < e:
             f = np.nextafter(f, np.float32(np.inf))
         out[i] = f
+    out.flags.writeable = False
     return out
 
 
@@ -175,9 +183,14 @@ def cell_stats(n, s1, s2, n_total, sigma_mode):
     mm = mm + m[2] * m[2]
     dev = e2 - mm
     dev = np.where(ok & (dev > 0.0), dev, 0.0)
-    q = np.rint((dev * nd) * 1048576.0).astype(np.int64)
-    qsum = int(q.sum(dtype=np.int64))
-    sg2 = float(np.float64(qsum) / ((3.0 * float(n_total)) * 1048576.0))
+    # global dispersion: per-cell fixed-point terms n dev 2^20 (each below 2^54, beyond which the
+    # step reports an overflow), summed exactly (Python integers) and rounded once to FP64
+    term = (dev * nd) * 1048576.0
+    if np.any(term >= 2.0**54):
+        raise OverflowError("a cell's n x dispersion term reaches 2^54")
+    q = np.rint(term).astype(np.int64)
+    qsum = int(q.astype(object).sum())
+    sg2 = float(qsum) / ((3.0 * float(n_total)) * 1048576.0)
     if not sg2 > 0.0:
         sg2 = 2.0**-60
     if sigma_mode == SIGMA_PER_CELL:

@@ -12,7 +12,7 @@ import atexit
 import ctypes
 import os
 import weakref
-from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_int64,
+from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_uint32,
                     c_size_t, c_uint64, c_void_p)
 
 import numpy as np
@@ -34,7 +34,7 @@ EXPORTED = [
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
     "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent", "cube_set_adaptive",
-    "cube_get_adaptive_log", "cube_get_last_maxima",
+    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).argtypes = [sim_p]
     lib.cube_load_particles.argtypes = [sim_p, c_void_p, c_void_p, c_int64]
     lib.cube_step.argtypes = [sim_p, c_int32]
+    lib.cube_debug_inject_flag.argtypes = [sim_p, c_int32, c_uint32]
     lib.cube_scale_factor.argtypes = [sim_p]
     lib.cube_scale_factor.restype = c_double
     lib.cube_steps_done.argtypes = [sim_p]
@@ -315,10 +316,21 @@ class Sim:
     def n(self) -> int:
         return self._lib.cube_num_particles(self._h)
 
-    def get_density(self) -> np.ndarray:
+    def get_density(self, device: bool = False):
+        """CIC density contrast [z, y, x]: a numpy array, or with device=True a torch tensor on the
+        simulation's GPU that the library writes directly (device-to-device)."""
+        if device:
+            import torch
+            out = torch.empty((self.nm,) * 3, dtype=torch.float32, device="cuda")
+            self._check(self._lib.cube_get_density(self._h, c_void_p(out.data_ptr()), 1))
+            return out
         out = np.empty((self.nm,) * 3, dtype=np.float32)
         self._check(self._lib.cube_get_density(self._h, _ptr(out), 0))
         return out
+
+    def debug_inject_flag(self, step: int, flag: int):
+        """Raise device error bits before the move of `step` (tests of the error path); -1: off."""
+        self._check(self._lib.cube_debug_inject_flag(self._h, step, flag))
 
     def get_power(self, nbins: int | None = None):
         nb = nbins or self.nm // 2

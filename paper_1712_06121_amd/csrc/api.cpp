@@ -173,7 +173,9 @@ int enqueue_adaptive(Sim& s, int k) {
       s.a_int.push_back(s.a_int[1] >= af ? af : adaptive_next(s, s.a_int[1], v0, 0.0));
       s.a_half.assign(1, std::sqrt(s.a_int[0] * s.a_int[1]));
       s.drift0 = s.cosmo.drift(s.a_int[0], s.a_half[0]);
+      s.phases.push_back({1u, s.cur, s.steps_done, false});
       launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+      launch_step_end(s, s.stream, 1u, false);
       s.half_drift_done = true;
     }
     const int j = s.steps_done;
@@ -184,9 +186,12 @@ int enqueue_adaptive(Sim& s, int k) {
     s.a_half[j + 1] = ah;
     s.kicks[j] = s.cosmo.kick(s.a_int[j], s.a_int[j + 1]);
     s.drifts[j] = s.cosmo.drift(s.a_half[j], ah);
+    s.phases.push_back({(uint32_t)j + 2u, s.cur, j, true});
     launch_deposit(s, s.stream);
     fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+    if (s.inject_step == j) launch_raise_flag(s, s.stream, s.inject_flag);
     launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream, nullptr);
+    launch_step_end(s, s.stream, (uint32_t)j + 2u, false);
     double vm = 0.0, gm = 0.0;
     read_maxima(s, &vm, &gm);
     check_flags(s);  // the step has been waited for anyway: stop at a failed step, not after k
@@ -200,16 +205,33 @@ int enqueue_adaptive(Sim& s, int k) {
 }
 
 void check_flags(Sim& s) {
-  uint32_t f = 0;
-  CUBE_HIP(hipMemcpyAsync(&f, s.flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s.stream));
+  uint32_t f[2] = {0u, 0u};
+  CUBE_HIP(hipMemcpyAsync(f, s.flags, sizeof(f), hipMemcpyDeviceToHost, s.stream));
   CUBE_HIP(hipStreamSynchronize(s.stream));
-  if (!f) return;
-  CUBE_HIP(hipMemsetAsync(s.flags, 0, sizeof(uint32_t), s.stream));
+  std::vector<Sim::PhaseRec> log;
+  log.swap(s.phases);
+  if (!f[0]) return;
+  // a link pass that returned early has left the count pass's sums in the moment accumulators
+  CUBE_HIP(hipMemsetAsync(s.flags, 0, 2 * sizeof(uint32_t), s.stream));
+  CUBE_HIP(hipMemsetAsync(s.mom, 0, sizeof(int64_t) * 4 * s.nc3, s.stream));
   CUBE_HIP(hipStreamSynchronize(s.stream));
-  if (f & FLAG_NONFINITE) throw Error{CUBE_E_NONFINITE, "non-finite particle position or velocity"};
-  if (f & FLAG_CFL) throw Error{CUBE_E_CFL, "a particle moved more than one coarse cell in one step"};
-  if (f & FLAG_OVERFLOW) throw Error{CUBE_E_OVERFLOW, "velocity outside the range of the moment accumulators"};
-  if (f & FLAG_COUNT) throw Error{CUBE_E_STATE, "particle count changed during the move"};
+  // the failing phase and every later one were not applied: back to the state before it
+  std::string where;
+  for (const Sim::PhaseRec& r : log) {
+    if (r.code != f[1]) continue;
+    s.cur = r.cur_before;
+    s.steps_done = r.steps_done_before;
+    s.half_drift_done = r.half_before;
+    where = r.code == 1u ? " (in the initial half drift; the state is the one before it)"
+                         : " (in step " + std::to_string(r.code - 2u) + "; the state is the one before that step)";
+    break;
+  }
+  if (f[0] & FLAG_NONFINITE) throw Error{CUBE_E_NONFINITE, "non-finite particle position or velocity" + where};
+  if (f[0] & FLAG_CFL) throw Error{CUBE_E_CFL, "a particle moved more than one coarse cell in one step" + where};
+  if (f[0] & FLAG_OVERFLOW)
+    throw Error{CUBE_E_OVERFLOW, "velocity or dispersion outside the range of the fixed-point accumulators" + where};
+  if (f[0] & FLAG_COUNT) throw Error{CUBE_E_STATE, "particle count changed during the move" + where};
+  throw Error{CUBE_E_STATE, "unknown device error flag" + where};
 }
 
 void copy_mesh_out(Sim& s, float* dst, hipMemcpyKind kind) {
@@ -304,18 +326,23 @@ int enqueue_steps(Sim& s, int k) {
       break;
     }
     if (!s.half_drift_done) {
+      s.phases.push_back({1u, s.cur, s.steps_done, false});
       launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+      launch_step_end(s, s.stream, 1u, false);
       s.half_drift_done = true;
     }
     const int j = s.steps_done;
+    s.phases.push_back({(uint32_t)j + 2u, s.cur, j, true});
     // profiling events: [0,1] deposit, [2..7] five FFT passes, [8..11] count, link, scatter
     hipEvent_t* ev = s.profiling ? s.ev : nullptr;
     if (ev) CUBE_HIP(hipEventRecord(ev[0], s.stream));
     launch_deposit(s, s.stream);
     if (ev) CUBE_HIP(hipEventRecord(ev[1], s.stream));
     fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, ev ? ev + 2 : nullptr);
+    if (s.inject_step == j) launch_raise_flag(s, s.stream, s.inject_flag);
     launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream,
                 ev ? ev + 8 : nullptr);
+    launch_step_end(s, s.stream, (uint32_t)j + 2u, false);
     if (ev) {
       CUBE_HIP(hipEventSynchronize(ev[11]));
       const int pairs[9][2] = {{0, 1}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7}, {8, 9}, {9, 10}, {10, 11}};
@@ -387,6 +414,7 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
   try {
     s.p = *params;
     s.stream = static_cast<hipStream_t>(stream);
+    CUBE_HIP(hipGetDevice(&s.device));
     if (alloc && alloc->alloc && alloc->free) {
       s.alloc = *alloc;
       s.has_alloc = true;
@@ -586,6 +614,17 @@ int cube_step(cube_sim* sim, int32_t k) {
 }
 
 
+int cube_debug_inject_flag(cube_sim* sim, int32_t step, uint32_t flag) {
+  if (!sim) return CUBE_E_INVALID;
+  const uint32_t known = cube::FLAG_CFL | cube::FLAG_NONFINITE | cube::FLAG_OVERFLOW | cube::FLAG_COUNT;
+  if (step < -1 || (flag & ~known) != 0u)
+    return cube::fail(sim, Error{CUBE_E_INVALID, "step must be >= -1 and flag a combination of the error bits"});
+  sim->s.inject_step = step;
+  sim->s.inject_flag = flag;
+  sim->s.config_gen++;  // captured step graphs hold the previous injection
+  return CUBE_OK;
+}
+
 double cube_scale_factor(const cube_sim* sim) {
   if (!sim) return 0.0;
   const cube::Sim& s = sim->s;
@@ -625,9 +664,15 @@ int cube_stage_move(cube_sim* sim, float kfac, float dfac) {
   if (!sim) return CUBE_E_INVALID;
   CUBE_GUARD(sim, {
     cube::require_particles(sim->s);
+    const int cur0 = sim->s.cur;
     cube::launch_move(sim->s, 0, kfac, dfac, nullptr, 0.0f, sim->s.stream, nullptr);
     CUBE_HIP(hipStreamSynchronize(sim->s.stream));
-    cube::check_flags(sim->s);
+    try {
+      cube::check_flags(sim->s);
+    } catch (const Error&) {
+      sim->s.cur = cur0;  // the failed move was not applied
+      throw;
+    }
   });
   return CUBE_OK;
 }

@@ -49,11 +49,13 @@ int batch_fail(cube_batch* b, const Error& e) {
   }
 
 // one step of a box on stream st with the factors taken from the device schedule
+// (the step-end kernel records a failure under the device step counter's code and advances it)
 void enqueue_graph_step(Sim& s, hipStream_t st) {
   launch_deposit(s, st);
   fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), st, nullptr);
+  if (s.inject_step >= 0) launch_raise_flag(s, st, s.inject_flag, true, s.inject_step);
   launch_move(s, 0, 0.0f, 0.0f, nullptr, 0.0f, st, nullptr, true);
-  launch_advance_step(s, st);
+  launch_step_end(s, st, 0u, true);
 }
 
 void destroy_graphs(cube_batch& b) {
@@ -140,7 +142,7 @@ void autotune_sim(Sim& s) {
   // deposit: particle order and workgroup size
   int best_d = s.deposit_variant;
   float best = 1e30f;
-  for (int v = 0; v < 4; ++v) {
+  for (int v : {0, 1, 2, 3, 4, 6}) {
     s.deposit_variant = v;
     const float t = timed([&] { launch_deposit(s, s.stream); });
     if (t < best) {
@@ -261,7 +263,7 @@ int cube_set_variant(cube_sim* sim, const cube_variant* v) {
   else if (std::find(ok.begin(), ok.end(), v->fft_col_width) == ok.end())
     err = "unsupported FFT column width for this mesh size";
   else if (v->fft_z_order < 0 || v->fft_z_order > 1) err = "fft_z_order must be 0 or 1";
-  else if (v->deposit_variant < 0 || v->deposit_variant > 3) err = "deposit_variant must be in 0..3";
+  else if (v->deposit_variant < 0 || v->deposit_variant > 7) err = "deposit_variant must be in 0..7";
   else if (v->fft_z_layout < 0 || v->fft_z_layout > 1) err = "fft_z_layout must be 0 or 1";
   else if (std::find(ok.begin(), ok.end(), v->fft_z_width) == ok.end() || v->fft_col_width % v->fft_z_width != 0)
     err = "fft_z_width must be a supported width dividing fft_col_width";
@@ -418,7 +420,9 @@ int cube_batch_step(cube_batch* b, int32_t k) {
     for (size_t i = 0; i < ss.size(); ++i) {
       cube::Sim& s = *ss[i];
       if (!s.half_drift_done) {
+        s.phases.push_back({1u, s.cur, s.steps_done, false});
         cube::launch_move(s, 1, 0.0f, (float)s.drift0, nullptr, 0.0f, s.stream, nullptr);
+        cube::launch_step_end(s, s.stream, 1u, false);
         s.half_drift_done = true;
       }
     }
@@ -435,6 +439,7 @@ int cube_batch_step(cube_batch* b, int32_t k) {
         rc = CUBE_DONE;
         break;
       }
+      for (cube::Sim* s : ss) s->phases.push_back({(uint32_t)s->steps_done + 2u, s->cur, s->steps_done, true});
       if (b->mode == 0) {
         cube::check_graphs(*b);
         const int par = ss[0]->cur;
@@ -456,13 +461,21 @@ int cube_batch_step(cube_batch* b, int32_t k) {
         CUBE_HIP(hipStreamWaitEvent(b->main, b->joins[bi], 0));
       }
     CUBE_HIP(hipStreamSynchronize(b->main));
+    // every box's flags are checked (a failed box goes back to the state before its failing step,
+    // the others keep their steps); the first failure is reported
+    std::string first;
+    int first_code = CUBE_OK;
     for (size_t i = 0; i < ss.size(); ++i) {
       try {
         cube::check_flags(*ss[i]);
       } catch (const Error& e) {
-        throw Error{e.code, "box " + std::to_string(i) + ": " + e.msg};
+        if (first_code == CUBE_OK) {
+          first_code = e.code;
+          first = "box " + std::to_string(i) + ": " + e.msg;
+        }
       }
     }
+    if (first_code != CUBE_OK) throw Error{first_code, first};
   });
   return rc;
 }

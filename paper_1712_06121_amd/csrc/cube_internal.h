@@ -67,6 +67,7 @@ struct FFTPlan {
 struct Sim {
   cube_params p{};
   hipStream_t stream = nullptr;
+  int device = 0;  // the HIP device the simulation was created on
   cube_allocator alloc{};
   bool has_alloc = false;
   std::string last_error;
@@ -137,6 +138,21 @@ struct Sim {
   double a_now = 0.0;
   bool have_particles = false;
 
+  // phases (the initial half drift, steps) enqueued since the flags were last checked, with the
+  // bookkeeping to restore when one of them fails: the device records the code of the first failing
+  // phase in flags[1] (1: the initial half drift, j + 2: step j), and no later phase is applied
+  struct PhaseRec {
+    uint32_t code;
+    int cur_before;
+    int steps_done_before;
+    bool half_before;
+  };
+  std::vector<PhaseRec> phases;
+  // failure injection for tests of the error path: raise inject_flag before the move of step
+  // inject_step (-1: never)
+  int inject_step = -1;
+  uint32_t inject_flag = 0;
+
   // profiling: per-kernel event pairs recorded on the simulation's stream
   bool profiling = false;
   hipEvent_t ev[16] = {};
@@ -183,7 +199,12 @@ void launch_deposit(Sim& s, hipStream_t st);
 // dev_sched: take the kick/drift factors of step *step_dev from sched_dev (for captured graphs)
 void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
                  hipEvent_t* evs, bool dev_sched = false);
-void launch_advance_step(Sim& s, hipStream_t st);
+// End of a phase of the run: records `code` in flags[1] if the flags are set and no earlier phase
+// failed; with dev_sched the code is that of the step counter (+2), which is then advanced.
+void launch_step_end(Sim& s, hipStream_t st, uint32_t code, bool dev_sched);
+// flags[0] |= f (the failure injection of tests); with dev_sched only when the device step
+// counter equals `at`
+void launch_raise_flag(Sim& s, hipStream_t st, uint32_t f, bool dev_sched = false, int at = 0);
 void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream_t st);
 // 1-byte counts into rho1 (nc3 bytes, device) and the counts >= 255 in cell order into over
 // (nc3 entries at most, device); returns the number of the latter

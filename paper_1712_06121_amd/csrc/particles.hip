@@ -46,6 +46,23 @@ __device__ __forceinline__ int wrapi(int x, int n) { return x < 0 ? x + n : (x >
 
 __device__ __forceinline__ void set_flag(uint32_t* flags, uint32_t f) { atomicOr(flags, f); }
 
+// number of lanes below this one in the wave mask m
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// A step whose error flags are set is not applied: the kernels that write the next state (link,
+// scan, cell statistics, scatter) return at once, so the state stays the one before the failing
+// step, and so it does through every later step enqueued behind it. The flag word is read once per
+// workgroup (through LDS), so all of a workgroup's waves take the same branch even when another
+// workgroup raises a flag meanwhile.
+__device__ __forceinline__ bool workgroup_step_failed(const uint32_t* flags) {
+  __shared__ uint32_t failed;
+  if (threadIdx.x == 0) failed = __atomic_load_n(flags, __ATOMIC_RELAXED);
+  __syncthreads();
+  return failed != 0u;
+}
+
 // exclusive prefix of up to 256 uint32 values held one per thread; returns the total
 __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* out, int n, uint32_t* wsum) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -340,6 +357,269 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   }
 }
 
+// Deposit with the source cells of a layer in three groups: the 36 interior cells of the column
+// (their CIC corners always fall inside it), the 28 other own cells, and the 36 ring cells, of
+// whose particles only those within half a fine cell of the column reach it. A wavefront takes 64
+// consecutive particles of a group; a lane's source cell follows from the group's prefix counts
+// by a forward walk shared by the wavefront. Interior particles of the layers whose planes all
+// belong to the workgroup deposit with no bounds tests. Ring particles are first tested, and the
+// ones that reach the column are packed into a queue held one per lane (a permutation of the
+// lanes, no LDS memory) that is deposited once 64 have gathered. The sums are exact integers, so
+// the order of the additions does not matter: the density is that of k_deposit, bit for bit.
+constexpr int DQ_INT = 36;   // interior own cells (x, y in 1..6)
+constexpr int DQ_OWN = 64;   // own cells
+__device__ __forceinline__ void dq_cell(int e, int& sx, int& sy) {
+  if (e < DQ_INT) {
+    sx = 1 + e % 6;
+    sy = 1 + e / 6;
+  } else if (e < DQ_OWN) {
+    const int b = e - DQ_INT;  // rows y = 0 and 7, then columns x = 0 and 7 for y in 1..6
+    if (b < 8) { sx = b; sy = 0; }
+    else if (b < 16) { sx = b - 8; sy = 7; }
+    else if (b < 22) { sx = 0; sy = b - 15; }
+    else { sx = 7; sy = b - 21; }
+  } else {
+    const int r = e - DQ_OWN;  // ring: rows y = -1 and 8 (x in -1..8), then columns x = -1 and 8 (y in 0..7)
+    if (r < 10) { sx = r - 1; sy = -1; }
+    else if (r < 20) { sx = r - 11; sy = 8; }
+    else if (r < 28) { sx = -1; sy = r - 20; }
+    else { sx = 8; sy = r - 28; }
+  }
+}
+
+template <int NCHI, int BLK>
+__global__ __launch_bounds__(BLK) void k_deposit_q(DepArgs a) {
+  using CT = chi_t<NCHI>;
+  constexpr int SH = 8 * NCHI - 1;
+  constexpr int NW = BLK / 64;
+  __shared__ unsigned long long rho[NSLOT * DF * DF];
+  __shared__ uint32_t pre[DRC + 1];
+  __shared__ uint64_t start[DRC];
+  __shared__ uint8_t sxy[DRC];  // (sx + 1) | (sy + 1) << 4 of each entry
+  __shared__ uint32_t wsum[NW];
+  __shared__ uint32_t smax;
+  const unsigned lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const unsigned bxy = lb % gridDim.x, bz = lb / gridDim.x;
+  const int cx0 = (bxy % a.nt) * DTX, cy0 = (bxy / a.nt) * DTX;
+  const int cz0 = bz * a.zc;
+  const int cz1 = min(cz0 + a.zc, a.nc);
+  const int pz0 = 4 * cz0, pz1 = 4 * cz1;  // owned fine planes [pz0, pz1)
+  for (int i = threadIdx.x; i < NSLOT * DF * DF; i += BLK) rho[i] = 0ull;
+  if (threadIdx.x == 0) smax = 0u;
+  if (threadIdx.x < DRC) {
+    int sx, sy;
+    dq_cell(threadIdx.x, sx, sy);
+    sxy[threadIdx.x] = (uint8_t)((sx + 1) | ((sy + 1) << 4));
+  }
+  __syncthreads();
+  // 32-bit accumulators when every source cell holds at most 255 particles (1-byte codes): a fine
+  // cell then receives less than 8 * 255 * 2^21 < 2^32
+  if constexpr (NCHI == 1) {
+    uint32_t m = 0u;
+    const int ncell = DRC * (cz1 - cz0 + 2);
+    for (int i = threadIdx.x; i < ncell; i += BLK) {
+      const int t = i % DRC, sz = cz0 - 1 + i / DRC;
+      const int sx = t % DR - 1, sy = t / DR - 1;
+      const uint32_t c = a.cnt[wrapi(cx0 + sx, a.nc) + (int64_t)a.nc * (wrapi(cy0 + sy, a.nc) + (int64_t)a.nc * wrapi(sz, a.nc))];
+      m = c > m ? c : m;
+    }
+    atomicMax(&smax, m);
+  }
+  __syncthreads();
+  const bool narrow = NCHI == 1 && smax <= 255u;
+  uint32_t* rho32 = reinterpret_cast<uint32_t*>(rho);
+  const CT* cx = static_cast<const CT*>(a.chi);
+  const CT* cy = cx + a.cap;
+  const CT* cz = cy + a.cap;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int sz = cz0 - 1; sz <= cz1; ++sz) {
+    uint32_t cntv = 0;
+    if (threadIdx.x < DRC) {
+      const int sx = (sxy[threadIdx.x] & 15) - 1, sy = (sxy[threadIdx.x] >> 4) - 1;
+      const int64_t c = wrapi(cx0 + sx, a.nc) + (int64_t)a.nc * (wrapi(cy0 + sy, a.nc) + (int64_t)a.nc * wrapi(sz, a.nc));
+      cntv = a.cnt[c];
+      start[threadIdx.x] = a.off[c];
+    }
+    block_exclusive_scan(cntv, pre, DRC, wsum);  // ends with a barrier
+    // slot of plane 4 sz - 1 + r for r in 0..5 (the planes this layer touches): (s0 + r) mod 6
+    const int s0 = slot_of(4 * sz - 1);
+    // the layer's planes all belong to the workgroup: no z tests
+    const bool zin = 4 * sz - 1 >= pz0 && 4 * sz + 4 < pz1;
+    auto run = [&](auto* acc) {
+      using A = typename std::remove_pointer<decltype(acc)>::type;
+      // CIC of one particle of source cell (sx, sy) with codes ch; CXY / CZ: test the corners
+      auto deposit = [&](auto cxy, auto cz_, const int sx, const int sy, const int* ch) {
+        constexpr bool CXY = decltype(cxy)::value, CZ = decltype(cz_)::value;
+        const int sl[3] = {sx, sy, sz};
+        int i0[3], w1[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int pl = sl[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
+          i0[d] = pl >> SH;
+          w1[d] = pl & ((1 << SH) - 1);
+        }
+        const uint32_t wz2[2] = {(uint32_t)((1 << SH) - w1[2]), (uint32_t)w1[2]};
+        const uint32_t wy2[2] = {(uint32_t)((1 << SH) - w1[1]), (uint32_t)w1[1]};
+        const uint32_t wx2[2] = {(uint32_t)((1 << SH) - w1[0]), (uint32_t)w1[0]};
+        const int r = i0[2] - (4 * sz - 1);  // 0 .. 4
+        const int sa = s0 + r >= NSLOT ? s0 + r - NSLOT : s0 + r;
+        const int sb = sa + 1 == NSLOT ? 0 : sa + 1;
+        const int slot2[2] = {sa * DF * DF, sb * DF * DF};
+        const int base = i0[1] * DF + i0[0];
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz) {
+          if (CZ) {
+            const int pz = i0[2] + dz;
+            if (pz < pz0 || pz >= pz1) continue;
+          }
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy) {
+            if (CXY) {
+              const int y = i0[1] + dy;
+              if (y < 0 || y >= DF) continue;
+            }
+            const uint32_t wzy = wz2[dz] * wy2[dy];
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+              if (CXY) {
+                const int x = i0[0] + dx;
+                if (x < 0 || x >= DF) continue;
+              }
+              const A w = NCHI == 1 ? (A)(wzy * wx2[dx]) : (A)((unsigned long long)wzy * (unsigned long long)wx2[dx]);
+              atomicAdd(&acc[slot2[dz] + base + dy * DF + dx], w);
+            }
+          }
+        }
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
+      // entries [e0, e1): particles [pre[e0], pre[e1]) in windows of 64 per wavefront; body(i, act, e, p)
+      auto windows = [&](int e0, int e1, auto&& body) {
+        const uint32_t q0 = pre[e0], q1 = pre[e1];
+        int ec = e0;  // the cell of the window's first particle (wave-uniform, non-decreasing)
+        for (uint32_t w0 = q0 + 64u * (uint32_t)wave; w0 < q1; w0 += BLK) {
+          while ((uint32_t)__builtin_amdgcn_readfirstlane(pre[ec + 1]) <= w0) ++ec;
+          const uint32_t i = w0 + (uint32_t)lane;
+          int e = ec;
+          for (int k = ec + 1; k < e1; ++k) {
+            const uint32_t pk = (uint32_t)__builtin_amdgcn_readfirstlane(pre[k]);
+            if (pk >= w0 + 64u) break;
+            if (pk <= i) e = k;
+          }
+          const bool act = i < q1;
+          // lanes past the end read the window's first particle (cell ec holds it)
+          const int64_t p = act ? (int64_t)start[e] + (i - pre[e]) : (int64_t)start[ec] + (w0 - pre[ec]);
+          body(act, e, p);
+        }
+      };
+      auto load = [&](int64_t p, int* ch) {
+        ch[0] = (int)cx[p];
+        ch[1] = (int)cy[p];
+        ch[2] = (int)cz[p];
+      };
+      // interior own cells: no x/y tests (and no z tests for the layers inside the chunk)
+      windows(0, DQ_INT, [&](bool act, int e, int64_t p) {
+        int ch[3];
+        load(p, ch);
+        if (act) {
+          const int sx = (sxy[e] & 15) - 1, sy = (sxy[e] >> 4) - 1;
+          if (zin) deposit(F_{}, F_{}, sx, sy, ch);
+          else deposit(F_{}, T_{}, sx, sy, ch);
+        }
+      });
+      windows(DQ_INT, DQ_OWN, [&](bool act, int e, int64_t p) {
+        int ch[3];
+        load(p, ch);
+        if (act) {
+          const int sx = (sxy[e] & 15) - 1, sy = (sxy[e] >> 4) - 1;
+          if (zin) deposit(T_{}, F_{}, sx, sy, ch);
+          else deposit(T_{}, T_{}, sx, sy, ch);
+        }
+      });
+      // ring: the particles whose CIC cloud reaches the column, gathered into full wavefronts
+      uint32_t qa = 0u, qb = 0u;  // queue entry of this lane: sxy | codes (two words for 2-byte codes)
+      uint32_t qn = 0u;           // entries in lanes [0, qn) (wave-uniform)
+      auto unpack_deposit = [&](uint32_t wa, uint32_t wb) {
+        int ch[3];
+        if constexpr (NCHI == 1) {
+          ch[0] = (int)((wa >> 8) & 255u);
+          ch[1] = (int)((wa >> 16) & 255u);
+          ch[2] = (int)(wa >> 24);
+        } else {
+          ch[0] = (int)(wa >> 16);
+          ch[1] = (int)(wb & 65535u);
+          ch[2] = (int)(wb >> 16);
+        }
+        const int sx = (int)(wa & 15u) - 1, sy = (int)((wa >> 4) & 15u) - 1;
+        deposit(T_{}, T_{}, sx, sy, ch);
+      };
+      windows(DQ_OWN, DRC, [&](bool act, int e, int64_t p) {
+        int ch[3];
+        load(p, ch);
+        const uint32_t code = sxy[e];
+        const int sx = (int)(code & 15u) - 1, sy = (int)(code >> 4) - 1;
+        const int ix = (sx * (1 << (SH + 2)) + 2 * ch[0] + 1 - (1 << (SH - 1))) >> SH;
+        const int iy = (sy * (1 << (SH + 2)) + 2 * ch[1] + 1 - (1 << (SH - 1))) >> SH;
+        const int iz = (sz * (1 << (SH + 2)) + 2 * ch[2] + 1 - (1 << (SH - 1))) >> SH;
+        const bool take = act && ix >= -1 && ix < DF && iy >= -1 && iy < DF && iz + 1 >= pz0 && iz < pz1;
+        uint32_t wa, wb = 0u;
+        if constexpr (NCHI == 1) {
+          wa = code | ((uint32_t)ch[0] << 8) | ((uint32_t)ch[1] << 16) | ((uint32_t)ch[2] << 24);
+        } else {
+          wa = code | ((uint32_t)ch[0] << 16);
+          wb = (uint32_t)ch[1] | ((uint32_t)ch[2] << 16);
+        }
+        // the taken lanes to lanes [0, c) in lane order, the others after them: a permutation
+        const unsigned long long m = __ballot(take);
+        const uint32_t c = (uint32_t)__popcll(m);
+        const uint32_t dst = take ? lanes_below(m) : c + lanes_below(~m);
+        wa = (uint32_t)__builtin_amdgcn_ds_permute((int)(dst * 4u), (int)wa);
+        if constexpr (NCHI == 2) wb = (uint32_t)__builtin_amdgcn_ds_permute((int)(dst * 4u), (int)wb);
+        // behind the qn queued entries: lane j takes the gathered entry j - qn
+        const int src = (int)(((uint32_t)lane - qn) & 63u) * 4;
+        const uint32_t ra = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)wa);
+        const uint32_t rb = NCHI == 2 ? (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)wb) : 0u;
+        if (qn + c < 64u) {
+          if ((uint32_t)lane >= qn && (uint32_t)lane < qn + c) {
+            qa = ra;
+            qb = rb;
+          }
+          qn += c;
+        } else {
+          const uint32_t fa = (uint32_t)lane < qn ? qa : ra, fb = (uint32_t)lane < qn ? qb : rb;
+          unpack_deposit(fa, fb);
+          qa = ra;
+          qb = rb;
+          qn = qn + c - 64u;
+        }
+      });
+      if ((uint32_t)lane < qn) unpack_deposit(qa, qb);
+    };
+    if (narrow) run(rho32);
+    else run(rho);
+    __syncthreads();
+    // planes completed by this layer
+    const int f0 = max(4 * sz - 1, pz0), f1 = min(4 * sz + 2, pz1 - 1);
+    const int nplanes = f1 - f0 + 1;
+    for (int i = threadIdx.x; i < nplanes * DF * DF; i += BLK) {
+      const int pz = f0 + i / (DF * DF), e = i % (DF * DF);
+      const int y = e / DF, x = e - y * DF;
+      const int idx = slot_of(pz) * DF * DF + e;
+      double r;
+      if (narrow) {
+        r = (double)rho32[idx];
+        rho32[idx] = 0u;
+      } else {
+        r = (double)rho[idx];
+        rho[idx] = 0ull;
+      }
+      a.mesh[((int64_t)pz * a.nm + (4 * cy0 + y)) * a.pitch_f + (4 * cx0 + x)] = (float)(r * a.inv_mean - 1.0);
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Move passes. MODE 0: kick with the potential in the mesh + drift; MODE 1: drift only;
 // MODE 2: initial conditions (lattice + Zel'dovich displacement).
@@ -391,10 +671,6 @@ struct MoveArgs {
   uint32_t* amax;
 };
 
-// number of lanes below this one in the wave mask m
-__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
-  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
 
 __device__ __forceinline__ float wave_max(float x) {
 #pragma unroll
@@ -904,6 +1180,9 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   __shared__ uint32_t wsum[NTH / 64];
   __shared__ float edges_lds[NNU == 1 ? 256 : 1];
   __shared__ int16_t bucket_lds[NNU == 1 ? 1024 : 1];
+  // the flag word is requested first and tested after the set-up (the last barrier): a wave that
+  // returns then cannot hold up the others
+  const uint32_t failed = __atomic_load_n(a.flags, __ATOMIC_RELAXED);
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
@@ -915,6 +1194,7 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   const float* edges = (NNU == 1) ? edges_lds : a.tedge;
   const int16_t* bucket = (NNU == 1) ? bucket_lds : a.tbucket;
   const uint32_t total = own_cells<MODE>(a, g, pre, start, wsum);
+  if (__builtin_amdgcn_readfirstlane(failed)) return;  // a failed step is not applied
   CT* chi_n = static_cast<CT*>(a.chi_n);
   NT* nu_n = static_cast<NT*>(a.nu_n);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1004,6 +1284,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   __shared__ float edges_lds[(SCATTER && NNU == 1) ? 256 : 1];
   __shared__ int8_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];  // 1-byte codes fit int8
   const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
+  // scatter: the flag word is requested first and tested after the set-up (the last barrier)
+  const uint32_t failed = SCATTER ? __atomic_load_n(a.flags, __ATOMIC_RELAXED) : 0u;
   // mean velocity and decode scale of the tile's cells
   __shared__ float4 cellv[TC];
   uint32_t cnt_r = 0;  // particle count of own cell threadIdx.x
@@ -1089,6 +1371,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   if constexpr (!SCATTER)
     for (int i = threadIdx.x; i < TC * 4; i += NTH) omom[i] = 0ull;
   block_exclusive_scan(cnt_r, pre, TC, wsum);  // ends with a barrier
+  if (SCATTER && __builtin_amdgcn_readfirstlane(failed)) return;  // a failed step is not applied
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const unsigned long long lt = (1ull << lane) - 1ull;
@@ -1328,11 +1611,17 @@ struct LinkArgs {
   int nc;
   int64_t nc3;
   const uint32_t* cnt_direct;  // load path: counts given directly (no migration counts)
+  uint32_t* flags;
 };
+
+// the per-cell dispersion term n dev 2^20 stays below 2^54, so that the int64 sums of the 256 cells
+// of a link block cannot overflow; the sum over the blocks is exact in 128 bits (k_scan_blocks)
+constexpr double kDevTermLimit = 18014398509481984.0;  // 2^54
 
 __global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) {
   __shared__ unsigned long long sn[LINK_BLK];
   __shared__ long long sq[LINK_BLK];
+  if (workgroup_step_failed(a.flags)) return;
   const int64_t c = (int64_t)blockIdx.x * LINK_BLK + threadIdx.x;
   uint32_t n = 0;
   long long q = 0;
@@ -1376,7 +1665,13 @@ __global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) {
     a.vc_n[a.nc3 + c] = (float)m1;
     a.vc_n[2 * a.nc3 + c] = (float)m2;
     a.dev[c] = dev;
-    q = __double2ll_rn((dev * nd) * 1048576.0);
+    const double term = (dev * nd) * 1048576.0;
+    if (term < kDevTermLimit) {
+      q = __double2ll_rn(term);
+    } else {
+      atomicOr(a.flags, FLAG_OVERFLOW);
+      q = 0;
+    }
   }
   sn[threadIdx.x] = n;
   sq[threadIdx.x] = q;
@@ -1394,25 +1689,41 @@ __global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) {
   }
 }
 
-// single workgroup: exclusive scan of the per-block counts, global dispersion
+// Nearest FP64 value (ties to even) of the unsigned 128-bit integer hi 2^64 + lo. Above 2^64 the
+// value is shifted right into 64 bits with the shifted-out bits kept as a sticky lowest bit, which
+// keeps the rounding to 53 bits exact; a 64-bit unsigned conversion is one rounding of the exact sum
+// of its two halves.
+__device__ __forceinline__ double u128_to_double(unsigned long long hi, unsigned long long lo) {
+  if (hi == 0ull) return (double)lo;
+  const int s = 64 - __clzll((long long)hi);  // 1 .. 64
+  const unsigned long long keep = s == 64 ? hi : ((hi << (64 - s)) | (lo >> s));
+  const unsigned long long lost = s == 64 ? lo : (lo & ((1ull << s) - 1ull));
+  return ldexp((double)(keep | (lost != 0ull ? 1ull : 0ull)), s);
+}
+
+// single workgroup: exclusive scan of the per-block counts; the global dispersion, the exact sum of
+// the per-block int64 terms (each in [0, 2^62)) in 128 bits
 __global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* blk_n, const int64_t* blk_q, uint64_t* blk_off,
                                                       int64_t nblk, uint64_t* off_end, int64_t n_expect,
                                                       double* scal, uint32_t* flags) {
   __shared__ unsigned long long ps[1024];
-  __shared__ long long pq[1024];
+  __shared__ unsigned long long qh[1024], ql[1024];
+  if (workgroup_step_failed(flags)) return;
   const int tid = threadIdx.x;
   const int64_t per = (nblk + 1023) / 1024;
   const int64_t b0 = tid * per, b1 = (b0 + per < nblk) ? b0 + per : nblk;
-  unsigned long long s = 0;
-  long long qs = 0;
+  unsigned long long s = 0, hi = 0, lo = 0;
   for (int64_t b = b0; b < b1; ++b) {
     s += blk_n[b];
-    qs += blk_q[b];
+    const unsigned long long q = (unsigned long long)blk_q[b];
+    lo += q;
+    hi += lo < q ? 1ull : 0ull;
   }
   ps[tid] = s;
-  pq[tid] = qs;
+  qh[tid] = hi;
+  ql[tid] = lo;
   __syncthreads();
-  // inclusive scan (Hillis-Steele) of ps; tree sum of pq
+  // inclusive scan (Hillis-Steele) of ps; tree sum of the 128-bit dispersion terms
   for (int o = 1; o < 1024; o <<= 1) {
     unsigned long long add = (tid >= o) ? ps[tid - o] : 0ull;
     __syncthreads();
@@ -1425,14 +1736,18 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* blk_n, const int
     run += blk_n[b];
   }
   for (int o = 512; o > 0; o >>= 1) {
-    if (tid < o) pq[tid] += pq[tid + o];
+    if (tid < o) {
+      const unsigned long long l2 = ql[tid] + ql[tid + o];
+      qh[tid] += qh[tid + o] + (l2 < ql[tid] ? 1ull : 0ull);
+      ql[tid] = l2;
+    }
     __syncthreads();
   }
   if (tid == 0) {
     const unsigned long long total = ps[1023];
     *off_end = total;
     if ((int64_t)total != n_expect) atomicOr(flags, FLAG_COUNT);
-    double sg2 = (double)pq[0] / ((3.0 * (double)n_expect) * 1048576.0);
+    double sg2 = u128_to_double(qh[0], ql[0]) / ((3.0 * (double)n_expect) * 1048576.0);
     if (!(sg2 > 0.0)) sg2 = 8.673617379884035e-19;  // 2^-60
     scal[0] = sg2;
   }
@@ -1449,11 +1764,13 @@ struct FinArgs {
   int64_t nc3;
   int sigma_mode;
   double sq2pi;
+  const uint32_t* flags;
 };
 
 __global__ __launch_bounds__(LINK_BLK) void k_finalize(FinArgs a) {
   __shared__ uint32_t pre[LINK_BLK + 1];
   __shared__ uint32_t wsum[LINK_BLK / 64];
+  if (workgroup_step_failed(a.flags)) return;
   const int64_t c = (int64_t)blockIdx.x * LINK_BLK + threadIdx.x;
   const uint32_t n = (c < a.nc3) ? a.cnt_n[c] : 0u;
   block_exclusive_scan(n, pre, LINK_BLK, wsum);
@@ -1626,7 +1943,15 @@ void launch_deposit(Sim& s, hipStream_t st) {
   a.inv_mean = (double)s.nm * (double)s.nm * (double)s.nm / ((double)s.n * ldexp(1.0, 3 * (8 * s.nchi - 1)));
   a.interleave = s.deposit_variant & 1;
   const dim3 grid((unsigned)cols, (unsigned)nchunk);
-  if (s.deposit_variant & 2) {
+  if (s.deposit_variant & 4) {
+    if (s.deposit_variant & 2) {
+      if (s.nchi == 1) k_deposit_q<1, 512><<<grid, 512, 0, st>>>(a);
+      else k_deposit_q<2, 512><<<grid, 512, 0, st>>>(a);
+    } else {
+      if (s.nchi == 1) k_deposit_q<1, 256><<<grid, 256, 0, st>>>(a);
+      else k_deposit_q<2, 256><<<grid, 256, 0, st>>>(a);
+    }
+  } else if (s.deposit_variant & 2) {
     if (s.nchi == 1) k_deposit<1, 512><<<grid, 512, 0, st>>>(a);
     else k_deposit<2, 512><<<grid, 512, 0, st>>>(a);
   } else {
@@ -1649,6 +1974,7 @@ static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipS
   l.nc = s.nc;
   l.nc3 = s.nc3;
   l.cnt_direct = cnt_direct;
+  l.flags = s.flags;
   k_link<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(l);
   CUBE_HIP(hipGetLastError());
   k_scan_blocks<<<1, 1024, 0, st>>>(s.blk_n, s.blk_q, s.blk_off, s.nblk, s.off[nxt] + s.nc3, s.n, s.scal, s.flags);
@@ -1664,16 +1990,32 @@ static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipS
   f.nc3 = s.nc3;
   f.sigma_mode = s.p.sigma_mode;
   f.sq2pi = std::sqrt(2.0 / M_PI);
+  f.flags = s.flags;
   k_finalize<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(f);
   CUBE_HIP(hipGetLastError());
 }
 
-__global__ void k_advance_step(int* step) {
-  if (threadIdx.x == 0) step[0] += 1;
+__global__ void k_step_end(uint32_t* flags, int* step, uint32_t code) {
+  if (threadIdx.x != 0) return;
+  if (step) {
+    code = (uint32_t)step[0] + 2u;
+    step[0] += 1;
+  }
+  if (flags[0] != 0u && flags[1] == 0u) flags[1] = code;
 }
 
-void launch_advance_step(Sim& s, hipStream_t st) {
-  k_advance_step<<<1, 64, 0, st>>>(s.step_dev);
+void launch_step_end(Sim& s, hipStream_t st, uint32_t code, bool dev_sched) {
+  k_step_end<<<1, 64, 0, st>>>(s.flags, dev_sched ? s.step_dev : nullptr, code);
+  CUBE_HIP(hipGetLastError());
+}
+
+// flags[0] |= f, when step is null or the device step counter equals `at`
+__global__ void k_raise_flag(uint32_t* flags, const int* step, int at, uint32_t f) {
+  if (threadIdx.x == 0 && (!step || step[0] == at)) flags[0] |= f;
+}
+
+void launch_raise_flag(Sim& s, hipStream_t st, uint32_t f, bool dev_sched, int at) {
+  k_raise_flag<<<1, 64, 0, st>>>(s.flags, dev_sched ? s.step_dev : nullptr, at, f);
   CUBE_HIP(hipGetLastError());
 }
 

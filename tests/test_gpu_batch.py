@@ -91,6 +91,7 @@ VARIANTS = [dict(move_variant=0, fft_col_width=8), dict(move_variant=1, fft_col_
             dict(move_variant=2), dict(move_variant=3), dict(move_variant=-1),
             dict(move_variant=0, fft_col_width=16, fft_z_order=1), dict(move_variant=1, fft_col_width=16),
             dict(deposit_variant=1), dict(deposit_variant=2), dict(deposit_variant=3, fft_z_order=1),
+            dict(deposit_variant=4), dict(deposit_variant=6),
             dict(fft_z_layout=1), dict(fft_z_layout=1, fft_col_width=16),
             dict(fft_z_layout=1, fft_col_width=16, fft_z_width=8)]
 
@@ -105,7 +106,7 @@ def test_variants_are_bit_identical(lib, variant):
 def test_variant_validation(lib):
     with lib.Sim(**synth.WORKLOADS["c1_pm32"]) as s:
         before = s.variant
-        for bad in (dict(move_variant=4), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=7),
+        for bad in (dict(move_variant=4), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=8),
                     dict(fft_z_layout=2), dict(fft_col_width=8, fft_z_width=16)):
             with pytest.raises(lib.CubeError):
                 s.set_variant(**bad)
@@ -132,3 +133,22 @@ def test_batch_refuses_boxes_out_of_step(lib):
         with pytest.raises(lib.CubeError) as e:
             b.step(1)
         assert "same step" in str(e.value)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_failed_box_stops_at_its_step(lib, mode):
+    """A box whose step fails (a CFL error raised from the host before the move of step 2) stays at
+    the state before that step; the other boxes complete their steps."""
+    cfgs = small_ensemble()[:3]
+    with lib.Batch(cfgs) as b:
+        b.set_mode(mode)
+        b.init_ic()
+        b.boxes[1].debug_inject_flag(2, 1)
+        with pytest.raises(lib.CubeError) as e:
+            b.step(4)
+        assert e.value.code == -5 and "box 1" in str(e.value) and "step 2" in str(e.value)
+        assert [box.steps_done for box in b.boxes] == [4, 2, 4]
+        got = [box.get_state() for box in b.boxes]
+    assert_same(got[0], run_alone(lib, cfgs[0], 4), "box 0")
+    assert_same(got[1], run_alone(lib, cfgs[1], 2), "box 1")
+    assert_same(got[2], run_alone(lib, cfgs[2], 4), "box 2")

@@ -59,10 +59,14 @@ def np_for(nm):
     return next(p for p in (32, 48, 64, 96, 128, 192, 256) if p % (nm // 4) == 0)
 
 
+DEPOSIT_VARIANTS = [3, 4, 6]  # the default; source-cell groups with gathered ring particles (256, 512 threads)
+
+
+@pytest.mark.parametrize("variant", DEPOSIT_VARIANTS)
 @pytest.mark.parametrize("clumps", [0.4, 0.0])
 @pytest.mark.parametrize("nchi", [1, 2])
 @pytest.mark.parametrize("nm", [32, 64, 96, 128])
-def test_deposit_bit_exact(Sim, nchi, nm, clumps):
+def test_deposit_bit_exact(Sim, nchi, nm, clumps, variant):
     # clumped clouds put hundreds to thousands of particles in a coarse cell (64-bit LDS sums);
     # without clumps every cell holds fewer than 255 (the 32-bit sums of 1-byte codes)
     nc = nm // 4
@@ -71,14 +75,16 @@ def test_deposit_bit_exact(Sim, nchi, nm, clumps):
     ref = twin.load(x, v, nc, nchi, 1)
     with Sim(np_for(nm), nm, 100.0, x_bytes=nchi, capacity=n) as sim:
         sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
+        sim.set_variant(deposit_variant=variant)
         sim.stage_deposit()
         got = sim.get_mesh()
     exp = twin.delta_from_rho(twin.deposit_int(ref, nm), ref.n, nchi)
     assert np.array_equal(got, exp)
 
 
+@pytest.mark.parametrize("variant", DEPOSIT_VARIANTS)
 @pytest.mark.parametrize("n", [1, 37, 900])
-def test_deposit_sparse_bit_exact(Sim, n):
+def test_deposit_sparse_bit_exact(Sim, n, variant):
     # layers with no particle at all and layers with fewer particles than a workgroup has threads
     # (the deposit's software pipeline clamps its look-ahead to the layer's last particle)
     nm = 64
@@ -86,6 +92,26 @@ def test_deposit_sparse_bit_exact(Sim, n):
     ref = twin.load(x, v, nm // 4, 1, 1)
     with Sim(np_for(nm), nm, 100.0, capacity=n) as sim:
         sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
+        sim.set_variant(deposit_variant=variant)
+        sim.stage_deposit()
+        got = sim.get_mesh()
+    exp = twin.delta_from_rho(twin.deposit_int(ref, nm), ref.n, 1)
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("variant", DEPOSIT_VARIANTS)
+def test_deposit_dense_layers_bit_exact(Sim, variant):
+    """Many chunks of z layers per workgroup column (a 256^3 mesh: interior layers with no plane
+    tests) and ring cells with many particles, some at the very edge of their cell."""
+    nm = 256
+    n = 600000
+    x, v = synth.particle_cloud(91, n, nm, clump_frac=0.3, n_clumps=40, clump_radius=3.0)
+    x[:5000] = np.floor(x[:5000] / 4.0) * 4.0 + np.where(np.arange(5000)[:, None] % 2 == 0, 1e-6, 4.0 - 1e-6)
+    x = np.mod(x, nm)
+    ref = twin.load(x, v, nm // 4, 1, 1)
+    with Sim(np_for(nm), nm, 100.0, capacity=n) as sim:
+        sim.set_state(ref.cnt, ref.chi, ref.nu, ref.vc, ref.vs)
+        sim.set_variant(deposit_variant=variant)
         sim.stage_deposit()
         got = sim.get_mesh()
     exp = twin.delta_from_rho(twin.deposit_int(ref, nm), ref.n, 1)
@@ -175,3 +201,61 @@ def test_cfl_violation_reported(Sim):
         with pytest.raises(CubeError) as e:
             sim.stage_move(0.0, 50.0)
         assert e.value.code == -5
+
+
+@pytest.mark.parametrize("nchi", [1, 2])
+def test_get_density_host_and_device(Sim, nchi):
+    """cube_get_density into host memory and into device memory equals the FP32 density of the
+    exact integer CIC of the same state, element by element."""
+    nm, nc, n = 64, 16, 30011
+    x, v = synth.particle_cloud(61 + nchi, n, nm)
+    ref = twin.load(x, v, nc, nchi, 1)
+    exp = twin.delta_from_rho(twin.deposit_int(ref, nm), ref.n, nchi)
+    with Sim(np_for(nm), nm, 100.0, x_bytes=nchi, capacity=n) as sim:
+        sim.load_particles(x, v)
+        host = sim.get_density()
+        dev = sim.get_density(device=True)
+        assert dev.device.type == "cuda" and dev.dtype.is_floating_point
+        dev = dev.cpu().numpy()
+    assert np.array_equal(host, exp)
+    assert np.array_equal(dev, exp)
+
+
+def test_get_density_after_steps(Sim):
+    cfg = synth.WORKLOADS["c1_pm32"]
+    with Sim(**cfg) as sim:
+        sim.init_ic()
+        sim.step(10)
+        got = sim.get_density(device=True).cpu().numpy()
+        st = sim.get_state()
+    tw = twin_state(st, cfg["nc_side"], cfg["x_bytes"], cfg["v_bytes"])
+    assert np.array_equal(got, twin.delta_from_rho(twin.deposit_int(tw, cfg["nm_side"]), tw.n, tw.nchi))
+
+
+def test_failed_step_is_not_applied(Sim):
+    """A step whose move raises an error flag (a CFL error raised from the host before the move of
+    step 2 of step(5)) and every later step of the call are not applied: the call reports the step,
+    the state and the step count are those after 2 steps, and the run continues from there."""
+    from paper_1712_06121_amd import CubeError
+    cfg = synth.WORKLOADS["c1_pm32"]
+    with Sim(**cfg) as ref:
+        ref.init_ic()
+        ref.step(2)
+        s2, a2 = ref.get_state(), ref.a
+        ref.step(3)
+        s5 = ref.get_state()
+    with Sim(**cfg) as sim:
+        sim.init_ic()
+        sim.debug_inject_flag(2, 1)
+        with pytest.raises(CubeError) as e:
+            sim.step(5)
+        assert e.value.code == -5 and "step 2" in str(e.value)
+        assert sim.steps_done == 2 and sim.a == a2
+        got = sim.get_state()
+        for key in KEYS:
+            assert np.array_equal(got[key], s2[key]), key
+        sim.debug_inject_flag(-1, 0)
+        sim.step(3)
+        got = sim.get_state()
+    for key in KEYS:
+        assert np.array_equal(got[key], s5[key]), key

@@ -83,3 +83,17 @@ def test_pm_force_matches_direct_sum(r):
     assert np.all(np.abs(rad - 1) < 0.03), rad
     assert abs(rad.mean() - 1) < 0.01, rad.mean()
     assert max(tan) < 0.03
+
+
+def test_threaded_fft_path_agrees():
+    """The benchmark's host timing runs the Poisson solve through scipy.fft with several threads;
+    it agrees with the default numpy.fft path to rounding."""
+    import synth
+    delta = synth.random_field(3, 32).astype(np.float64)
+    ref = pm.poisson(delta, 0.3)
+    try:
+        pm.FFT_WORKERS = 4
+        got = pm.poisson(delta, 0.3)
+    finally:
+        pm.FFT_WORKERS = None
+    assert np.allclose(got, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
