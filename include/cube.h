@@ -169,6 +169,18 @@ int cube_get_density(cube_sim* sim, float* dst, int dst_on_device);
  * mean |k| (h/Mpc), mean P ((Mpc/h)^3, FP64 shell sums) and the number of modes. */
 int cube_get_power(cube_sim* sim, int32_t nbins, double* k, double* pk, double* nmodes);
 
+/* Allocation-free variant of cube_get_power, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same CIC
+ * deposit, forward FFT and shell sums, with the FP64 shell sums kept in a fixed array of the
+ * library (3 x 1025 doubles per device, held until the process ends) instead of the simulation's
+ * allocation, and the results written to DEVICE arrays k, pk, nmodes of nbins doubles each (mean |k|
+ * in h/Mpc, mean P in (Mpc/h)^3, mode counts). Everything is enqueued on the simulation's stream
+ * and nothing is waited for; the call allocates no device memory. Every call on one GPU shares
+ * that array and clears it first: calls that overlap on one GPU (simulations on different
+ * streams) race and must be ordered by the caller. Overwrites the mesh (scratch between steps).
+ * Errors: CUBE_E_INVALID (nbins outside [1, nm/2]), CUBE_E_STATE (no particles), CUBE_E_DEVICE. */
+int cube_get_power_noalloc(cube_sim* sim, int32_t nbins, double* k, double* pk, double* nmodes);
+
 /* Cross power spectrum of the current states of two simulations over the same box (Sec. 3,
  * Eq. (cps) with two fields; the cross-correlation coefficient of Eq. (ccc) is
  * pab / sqrt(paa pbb)). Both densities are CIC-deposited on their own meshes and transformed;

@@ -34,7 +34,7 @@ EXPORTED = [
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
     "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent", "cube_set_adaptive",
-    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag",
+    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag", "cube_get_power_noalloc",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -122,6 +122,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_num_particles.restype = c_int64
     lib.cube_get_density.argtypes = [sim_p, c_void_p, c_int]
     lib.cube_get_power.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
+    lib.cube_get_power_noalloc.argtypes = [sim_p, c_int32, c_void_p, c_void_p, c_void_p]
     lib.cube_get_cross_power.argtypes = [sim_p, sim_p, c_int32] + [c_void_p] * 5
     lib.cube_enable_pids.argtypes = [sim_p, c_int32]
     lib.cube_set_ic_parent.argtypes = [sim_p, c_int32]
@@ -327,6 +328,15 @@ class Sim:
         out = np.empty((self.nm,) * 3, dtype=np.float32)
         self._check(self._lib.cube_get_density(self._h, _ptr(out), 0))
         return out
+
+    def get_power_noalloc(self, k, pk, nmodes, nbins: int | None = None):
+        """cube_get_power_noalloc into caller-provided device tensors (float64, nbins each); the
+        library allocates nothing and does not synchronise."""
+        nb = nbins or self.nm // 2
+        for t in (k, pk, nmodes):
+            assert t.is_cuda and t.is_contiguous() and t.numel() >= nb and str(t.dtype) == "torch.float64"
+        self._check(self._lib.cube_get_power_noalloc(self._h, nb, c_void_p(k.data_ptr()), c_void_p(pk.data_ptr()),
+                                                     c_void_p(nmodes.data_ptr())))
 
     def debug_inject_flag(self, step: int, flag: int):
         """Raise device error bits before the move of `step` (tests of the error path); -1: off."""

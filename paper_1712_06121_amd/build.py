@@ -28,6 +28,7 @@ PER_FILE = {
     "cosmo.cpp": ["-ffp-contract=off"],
     "batch.cpp": ["-ffp-contract=off"],
     "serve.cpp": ["-ffp-contract=off"],
+    "noalloc.hip": ["-ffp-contract=off"],
 }
 
 

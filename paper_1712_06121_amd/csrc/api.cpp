@@ -415,6 +415,7 @@ int cube_create(const cube_params* params, void* stream, const cube_allocator* a
     s.p = *params;
     s.stream = static_cast<hipStream_t>(stream);
     CUBE_HIP(hipGetDevice(&s.device));
+    (void)cube::noalloc_scratch(s.device);  // set-up of the allocation-free entry point, once per device
     if (alloc && alloc->alloc && alloc->free) {
       s.alloc = *alloc;
       s.has_alloc = true;

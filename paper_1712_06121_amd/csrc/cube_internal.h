@@ -214,6 +214,9 @@ float launch_state_speed2(Sim& s, hipStream_t st);
 // particle IDs 0 .. n-1 in storage order (when IDs are enabled)
 void launch_pid_iota(Sim& s, hipStream_t st);
 void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmodes);
+// device address of the allocation-free entry point's fixed shell-sum array on device `dev`
+// (looked up once per device; noalloc.hip)
+double* noalloc_scratch(int dev);
 
 }  // namespace cube
 
