@@ -119,7 +119,9 @@ def cpu_baseline(steps: dict):
     from oracle import ic, pm
     from oracle.cosmology import Cosmology
 
-    threads = os.cpu_count() or 1
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():  # the host's share of the machine, where it is set
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     pm.FFT_WORKERS = threads
     per = {}
     try:
@@ -325,6 +327,7 @@ def main() -> int:
     ap.add_argument("--cpu-sibling-steps", type=int, default=2,
                     help="oracle steps timed on the 256^3 sibling of the 2048^3 workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-early-window", action="store_true", help="time only the last steps of the schedule")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel variants instead of timing the equivalent ones after warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -374,6 +377,7 @@ def main() -> int:
         sim.autotune()  # bit-identical variants; the fastest of each stage on this state
         torch.cuda.synchronize()
         print(f"[bench] autotune in {time.perf_counter() - t0:.1f} s: {sim.variant}", file=sys.stderr, flush=True)
+        print(f"[bench] autotune times: {sim.autotune_report}", file=sys.stderr, flush=True)
 
     def timed_window(k):
         """k steps with per-kernel HIP events; (wall seconds, kernel ms per step, scale factors)."""
@@ -393,9 +397,9 @@ def main() -> int:
     # schedule, ending at a = 1 (the clustered regime), which give `value`
     early = None
     n_total = cfg["n_steps"]
-    if args.warmup + 2 * args.steps <= n_total:
+    if args.warmup + 2 * args.steps <= n_total and not args.no_early_window:
         el, ms_e, a_e = timed_window(args.steps)
-        early = {"steps": args.steps, "a": a_e, "ms_per_step": 1e3 * el / args.steps,
+        early = {"steps": args.steps, "a": a_e, "ms_per_step": 1e3 * el / args.steps, "variants": dict(sim.variant),
                  "value": cfg["np_side"] ** 3 * args.steps / el, "kernels_ms": ms_e}
         print(f"[bench] early window a={a_e[0]:.3f}..{a_e[1]:.3f}: {1e3 * el / args.steps:.1f} ms/step",
               file=sys.stderr, flush=True)
@@ -406,6 +410,15 @@ def main() -> int:
         torch.cuda.synchronize()
         skip -= k
         print(f"[bench] untimed steps to {sim.steps_done} (a={sim.a:.3f})", file=sys.stderr, flush=True)
+    variants_early = sim.variant
+    if not args.no_autotune:
+        # the particles are far more clustered now: the variants are timed again on this state
+        t0 = time.perf_counter()
+        sim.autotune()
+        torch.cuda.synchronize()
+        print(f"[bench] autotune before the late window in {time.perf_counter() - t0:.1f} s: {sim.variant}",
+              file=sys.stderr, flush=True)
+        print(f"[bench] autotune times: {sim.autotune_report}", file=sys.stderr, flush=True)
     elapsed, ms, a_late = timed_window(args.steps)
     print(f"[bench] late window a={a_late[0]:.3f}..{a_late[1]:.3f}: {args.steps} timed steps in {elapsed:.3f} s",
           file=sys.stderr, flush=True)
@@ -480,6 +493,8 @@ def main() -> int:
             "v_bytes": cfg["v_bytes"],
             "sigma": "per-cell",
             "variants": sim.variant,
+            "variants_early": variants_early,
+            "device_bytes": sim.device_bytes,
         },
         "window": {"steps": args.steps, "a": a_late, "position": "last steps of the schedule, ending at a_final"},
         "early_window": early,

@@ -125,6 +125,23 @@ int cube_load_particles(cube_sim* sim, const double* x, const double* v, int64_t
  * more, or a coarse cell whose n x 3-D velocity variance reaches 2^34), CUBE_E_STATE. */
 int cube_step(cube_sim* sim, int32_t k);
 
+/* Two-level force (Sec. 2.3.1, 2.3.3, Fig. update_vp): the paper splits the force into a fine-mesh
+ * part whose kernel vanishes beyond the buffer region and a compensating part computed from the
+ * coarse density on a mesh R = 4 times coarser by one global FFT. With r_s > 0 every later Poisson
+ * solve (steps, cube_stage_solve) uses
+ *   phi(n) = G(n) [(1 - S(n)) D_f(n) + S(n) R^3 D_c(n) / B(n)]  for the modes with every |n_i| < N_c/2,
+ *   phi(n) = G(n) (1 - S(n)) D_f(n)                              for the others,
+ * with G = -3/2 Omega_m / k^2, S = exp(-k^2 r_s^2) (k in rad per fine cell), D_f the fine density's
+ * spectrum, D_c that of its restriction to the coarse mesh with tent weights (1,3,5,7,7,5,3,1)/32 over
+ * fine offsets -2..5 along each axis, and B the restriction's transfer: the fine part (kernel
+ * G (1 - S), short-ranged: erfc(r / 2 r_s) / r) is solved by the fine-mesh FFT and the coarse part
+ * joins it in Fourier space. The force is then the single-level one's 4-point gradient and CIC
+ * interpolation. r_s in fine cells, between 4 (S negligible at the coarse Nyquist frequency) and
+ * nm_side / 4; 0 switches back to the single-level solve and frees the coarse buffers (one
+ * coarse-mesh FFT field, not counted by cube_footprint). Needs nc_side to be 16 or a supported FFT
+ * size. Errors: CUBE_E_INVALID, CUBE_E_NOMEM. */
+int cube_set_two_level(cube_sim* sim, double r_s);
+
 /* Failure injection for tests of the error path: raise the device error bits `flag` (1 CFL,
  * 2 non-finite, 4 overflow, 8 count) just before the move of step `step` of later cube_step or
  * cube_batch_step calls, as if that move had raised them; step -1 switches it off.
@@ -293,9 +310,7 @@ typedef struct {
                               per XCD */
   int32_t deposit_variant; /* bit 0: particles of a layer visited with a stride of 1/64 of the layer
                               (lanes of a wavefront in different cells); bit 1: 512-thread
-                              workgroups instead of 256; bit 2: source cells in three groups
-                              (interior, other own, ring) with the ring particles that reach the
-                              column gathered into full wavefronts (bit 0 ignored); default 3 */
+                              workgroups instead of 256; default 3 */
   int32_t fft_z_layout;    /* 0 (default): z pass in place on the mesh; 1: the forward y pass writes
                               a z-contiguous copy, the z pass works there and the inverse y pass
                               writes back (one more mesh-sized device buffer, allocated when chosen
@@ -307,6 +322,9 @@ typedef struct {
  * discarded) and keep the fastest of each stage. The particle state is unchanged; the mesh
  * afterwards holds the potential of the current state. Errors: CUBE_E_STATE (no particles). */
 int cube_autotune(cube_sim* sim);
+/* The times the last cube_autotune measured, one "stage variant t ms;" item per timed variant
+ * (text owned by the simulation; "" before the first call). */
+const char* cube_autotune_report(const cube_sim* sim);
 int cube_get_variant(const cube_sim* sim, cube_variant* out);
 /* Errors: CUBE_E_INVALID for a value outside the ranges above (nothing is changed then). */
 int cube_set_variant(cube_sim* sim, const cube_variant* v);

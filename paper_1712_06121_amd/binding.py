@@ -34,7 +34,7 @@ EXPORTED = [
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
     "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent", "cube_set_adaptive",
-    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag", "cube_get_power_noalloc",
+    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag", "cube_get_power_noalloc", "cube_autotune_report", "cube_set_two_level",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_load_particles.argtypes = [sim_p, c_void_p, c_void_p, c_int64]
     lib.cube_step.argtypes = [sim_p, c_int32]
     lib.cube_debug_inject_flag.argtypes = [sim_p, c_int32, c_uint32]
+    lib.cube_set_two_level.argtypes = [sim_p, c_double]
     lib.cube_scale_factor.argtypes = [sim_p]
     lib.cube_scale_factor.restype = c_double
     lib.cube_steps_done.argtypes = [sim_p]
@@ -147,6 +148,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_set_profiling.argtypes = [sim_p, c_int]
     lib.cube_get_timings.argtypes = [sim_p, c_void_p]
     lib.cube_autotune.argtypes = [sim_p]
+    lib.cube_autotune_report.argtypes = [sim_p]
+    lib.cube_autotune_report.restype = c_char_p
     lib.cube_get_variant.argtypes = [sim_p, POINTER(CubeVariant)]
     lib.cube_set_variant.argtypes = [sim_p, POINTER(CubeVariant)]
     batch_p = c_void_p
@@ -338,6 +341,10 @@ class Sim:
         self._check(self._lib.cube_get_power_noalloc(self._h, nb, c_void_p(k.data_ptr()), c_void_p(pk.data_ptr()),
                                                      c_void_p(nmodes.data_ptr())))
 
+    def set_two_level(self, r_s: float):
+        """Two-level force with split radius r_s (fine cells); 0 returns to the single-level solve."""
+        self._check(self._lib.cube_set_two_level(self._h, float(r_s)))
+
     def debug_inject_flag(self, step: int, flag: int):
         """Raise device error bits before the move of `step` (tests of the error path); -1: off."""
         self._check(self._lib.cube_debug_inject_flag(self._h, step, flag))
@@ -488,6 +495,11 @@ class Sim:
     def autotune(self):
         """Time the equivalent kernel variants on the current state and keep the fastest."""
         self._check(self._lib.cube_autotune(self._h))
+
+    @property
+    def autotune_report(self) -> str:
+        """The per-variant times of the last autotune (text)."""
+        return self._lib.cube_autotune_report(self._h).decode()
 
     @property
     def variant(self) -> dict:

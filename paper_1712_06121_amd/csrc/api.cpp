@@ -188,7 +188,7 @@ int enqueue_adaptive(Sim& s, int k) {
     s.drifts[j] = s.cosmo.drift(s.a_half[j], ah);
     s.phases.push_back({(uint32_t)j + 2u, s.cur, j, true});
     launch_deposit(s, s.stream);
-    fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+    solve_potential(s, s.stream);
     if (s.inject_step == j) launch_raise_flag(s, s.stream, s.inject_flag);
     launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream, nullptr);
     launch_step_end(s, s.stream, (uint32_t)j + 2u, false);
@@ -239,6 +239,26 @@ void copy_mesh_out(Sim& s, float* dst, hipMemcpyKind kind) {
   CUBE_HIP(hipMemcpy2DAsync(dst, sizeof(float) * s.nm, s.mesh, pitch, sizeof(float) * s.nm, (size_t)s.nm * s.nm, kind,
                             s.stream));
   CUBE_HIP(hipStreamSynchronize(s.stream));
+}
+
+// The Poisson solve of a step on the mesh. Two-level force (Sec. 2.3.3): the fine density is
+// restricted to the coarse mesh and transformed there, and the fused z pass of the fine solve
+// combines the short-range fine part with the compensating coarse part.
+void solve_potential(Sim& s, hipStream_t st, hipEvent_t* evs) {
+  if (s.two_level_rs > 0.0) {
+    launch_restrict(s.mesh_plan, s.mesh, s.coarse_plan, s.coarse, st);
+    fft_forward_3d(s.coarse_plan, s.coarse, st);
+    CoarseTerm ct;
+    ct.spec = reinterpret_cast<const float2*>(s.coarse);
+    ct.pitch_c = s.coarse_plan.pitch_c;
+    ct.half = s.nc / 2;
+    ct.rs2 = (float)(s.two_level_rs * s.two_level_rs);
+    ct.scale = 64.0f;  // R^3
+    ct.inv_b = s.inv_b;
+    fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), st, evs, &ct);
+  } else {
+    fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), st, evs);
+  }
 }
 
 float gconst(const Sim& s) {
@@ -338,7 +358,7 @@ int enqueue_steps(Sim& s, int k) {
     if (ev) CUBE_HIP(hipEventRecord(ev[0], s.stream));
     launch_deposit(s, s.stream);
     if (ev) CUBE_HIP(hipEventRecord(ev[1], s.stream));
-    fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, ev ? ev + 2 : nullptr);
+    solve_potential(s, s.stream, ev ? ev + 2 : nullptr);
     if (s.inject_step == j) launch_raise_flag(s, s.stream, s.inject_flag);
     launch_move(s, 0, (float)(-s.kicks[j] / 12.0), (float)s.drifts[j], nullptr, 0.0f, s.stream,
                 ev ? ev + 8 : nullptr);
@@ -615,6 +635,50 @@ int cube_step(cube_sim* sim, int32_t k) {
 }
 
 
+int cube_set_two_level(cube_sim* sim, double r_s) {
+  if (!sim) return CUBE_E_INVALID;
+  cube::Sim& s = sim->s;
+  if (!(r_s <= 0.0) && !(r_s >= 4.0 && r_s <= 0.25 * s.nm))
+    return cube::fail(sim, Error{CUBE_E_INVALID, "r_s must be 0 (off) or between 4 fine cells and nm_side / 4"});
+  if (r_s > 0.0 && !cube::fft_coarse_size_supported(s.nc))
+    return cube::fail(sim, Error{CUBE_E_INVALID, "the coarse mesh size is not a supported FFT size"});
+  CUBE_GUARD(sim, {
+    CUBE_HIP(hipStreamSynchronize(s.stream));
+    if (r_s <= 0.0) {
+      if (s.coarse) {
+        s.dfree(s.coarse);
+        s.dfree(s.inv_b);
+        cube::fft_plan_destroy(s, s.coarse_plan);
+        s.coarse = nullptr;
+        s.inv_b = nullptr;
+      }
+    } else if (!s.coarse) {
+      cube::fft_plan_create(s, s.coarse_plan, s.nc);
+      s.coarse = static_cast<float*>(s.dmalloc(s.coarse_plan.field_floats() * sizeof(float)));
+      // 1 / B(f): the restriction's transfer sum_b w_b exp(2 pi i f b / nm) over the tent weights
+      // (1, 3, 5, 7, 7, 5, 3, 1) / 32 at offsets b = -2 .. 5, for the signed coarse frequencies
+      const int h = s.nc / 2;
+      std::vector<float2> tab(s.nc, make_float2(0.0f, 0.0f));
+      const double w[8] = {1, 3, 5, 7, 7, 5, 3, 1};
+      for (int f = -h + 1; f < h; ++f) {
+        double re = 0.0, im = 0.0;
+        for (int b = -2; b <= 5; ++b) {
+          const double ang = 2.0 * M_PI * f * b / s.nm;
+          re += w[b + 2] / 32.0 * std::cos(ang);
+          im += w[b + 2] / 32.0 * std::sin(ang);
+        }
+        const double d = re * re + im * im;
+        tab[f + h] = make_float2((float)(re / d), (float)(-im / d));
+      }
+      s.inv_b = static_cast<float2*>(s.dmalloc(sizeof(float2) * s.nc));
+      CUBE_HIP(hipMemcpy(s.inv_b, tab.data(), sizeof(float2) * s.nc, hipMemcpyHostToDevice));
+    }
+    s.two_level_rs = r_s > 0.0 ? r_s : 0.0;
+    s.config_gen++;  // captured step graphs hold the previous solve
+  });
+  return CUBE_OK;
+}
+
 int cube_debug_inject_flag(cube_sim* sim, int32_t step, uint32_t flag) {
   if (!sim) return CUBE_E_INVALID;
   const uint32_t known = cube::FLAG_CFL | cube::FLAG_NONFINITE | cube::FLAG_OVERFLOW | cube::FLAG_COUNT;
@@ -655,7 +719,7 @@ int cube_stage_deposit(cube_sim* sim) {
 int cube_stage_solve(cube_sim* sim) {
   if (!sim) return CUBE_E_INVALID;
   CUBE_GUARD(sim, {
-    cube::fft_solve_poisson(sim->s.mesh_plan, sim->s.mesh, cube::gconst(sim->s), sim->s.stream);
+    cube::solve_potential(sim->s, sim->s.stream);
     CUBE_HIP(hipStreamSynchronize(sim->s.stream));
   });
   return CUBE_OK;

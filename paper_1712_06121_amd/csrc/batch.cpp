@@ -8,6 +8,7 @@
 // is replayed for every step; two graphs are kept, one per parity of the double-buffered state.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <map>
 #include <tuple>
 
@@ -52,7 +53,7 @@ int batch_fail(cube_batch* b, const Error& e) {
 // (the step-end kernel records a failure under the device step counter's code and advances it)
 void enqueue_graph_step(Sim& s, hipStream_t st) {
   launch_deposit(s, st);
-  fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), st, nullptr);
+  solve_potential(s, st);
   if (s.inject_step >= 0) launch_raise_flag(s, st, s.inject_flag, true, s.inject_step);
   launch_move(s, 0, 0.0f, 0.0f, nullptr, 0.0f, st, nullptr, true);
   launch_step_end(s, st, 0u, true);
@@ -101,14 +102,30 @@ void check_graphs(cube_batch& b) {
 }
 
 // z layout of the solve: 1 allocates the scratch copy (one mesh-sized buffer) if needed, 0 keeps
-// any allocated scratch, -1 selects 0 and frees the scratch
+// any allocated scratch, -1 selects 0 and frees the scratch. The scratch also holds the move
+// passes' per (cell, displacement) counts and slots (27 x 4 bytes each per coarse cell, less than
+// the mesh's 64 x 4): the copy is live only inside a solve, the counts and slots only inside a
+// move, so one buffer serves both and their own allocation is given back.
 void set_z_layout(Sim& s, int layout) {
   FFTPlan& pl = s.mesh_plan;
   s.config_gen++;
-  if (layout == 1 && !pl.zscratch) pl.zscratch = static_cast<float2*>(s.dmalloc(pl.field_floats() * sizeof(float)));
+  const size_t mig_bytes = sizeof(uint32_t) * 27 * (size_t)s.nc3;
+  if (layout == 1 && !pl.zscratch) {
+    const size_t zb = pl.field_floats() * sizeof(float);
+    char* w = static_cast<char*>(s.dmalloc(std::max(zb, 2 * mig_bytes)));
+    s.dfree(s.mig);
+    s.dfree(s.slot);
+    pl.zscratch = reinterpret_cast<float2*>(w);
+    s.mig = reinterpret_cast<uint32_t*>(w);
+    s.slot = reinterpret_cast<uint32_t*>(w + mig_bytes);
+  }
   if (layout < 0 && pl.zscratch) {
+    uint32_t* m = static_cast<uint32_t*>(s.dmalloc(mig_bytes));
+    uint32_t* sl = static_cast<uint32_t*>(s.dmalloc(mig_bytes));
     s.dfree(pl.zscratch);
     pl.zscratch = nullptr;
+    s.mig = m;
+    s.slot = sl;
   }
   pl.zlayout = layout > 0 ? 1 : 0;
 }
@@ -140,11 +157,18 @@ void autotune_sim(Sim& s) {
     return t;
   };
   // deposit: particle order and workgroup size
+  std::string rep;
+  auto note = [&](const std::string& what, float ms) {
+    char b[96];
+    std::snprintf(b, sizeof(b), "%s %.3f ms; ", what.c_str(), ms / reps);
+    rep += b;
+  };
   int best_d = s.deposit_variant;
   float best = 1e30f;
-  for (int v : {0, 1, 2, 3, 4, 6}) {
+  for (int v : {0, 1, 2, 3}) {
     s.deposit_variant = v;
     const float t = timed([&] { launch_deposit(s, s.stream); });
+    note("deposit " + std::to_string(v), t);
     if (t < best) {
       best = t;
       best_d = v;
@@ -176,7 +200,9 @@ void autotune_sim(Sim& s) {
           s.mesh_plan.zorder = z;
           s.mesh_plan.zlayout = l;
           launch_deposit(s, s.stream);
-          const float t = timed([&] { fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr); });
+          const float t = timed([&] { solve_potential(s, s.stream); });
+          note("solve layout " + std::to_string(l) + " width " + std::to_string(bx) + "/" + std::to_string(zb) +
+                   " order " + std::to_string(z), t);
           if (t < best) {
             best = t;
             best_bx = bx;
@@ -194,7 +220,7 @@ void autotune_sim(Sim& s) {
   if (best_l == 0 && !had_scratch) CUBE_HIP(hipStreamSynchronize(s.stream));
   set_z_layout(s, best_l == 0 && !had_scratch ? -1 : best_l);
   launch_deposit(s, s.stream);
-  fft_solve_poisson(s.mesh_plan, s.mesh, gconst(s), s.stream, nullptr);
+  solve_potential(s, s.stream);
   // move passes: per-corner gradient vs precomputed gradient tile, each pass timed on its own
   // (events around the count and the scatter pass), with this step's factors
   const int j = std::min(s.steps_done, s.p.n_steps - 1);
@@ -214,6 +240,11 @@ void autotune_sim(Sim& s) {
       }
     }
   }
+  for (int v = 0; v <= 1; ++v) {
+    note("count " + std::to_string(v), tc[v]);
+    note("scatter " + std::to_string(v), ts[v]);
+  }
+  s.autotune_report = rep;
   const bool tcnt = tc[1] < tc[0], tsct = ts[1] < ts[0];
   s.move_variant = tcnt ? (tsct ? 1 : 3) : (tsct ? 2 : 0);
   // a timed move may have raised a flag that the real step will raise again; clear it here
@@ -242,6 +273,8 @@ int cube_autotune(cube_sim* sim) {
   return CUBE_OK;
 }
 
+const char* cube_autotune_report(const cube_sim* sim) { return sim ? sim->s.autotune_report.c_str() : ""; }
+
 int cube_get_variant(const cube_sim* sim, cube_variant* out) {
   if (!sim || !out) return CUBE_E_INVALID;
   const cube::Sim& s = sim->s;
@@ -263,7 +296,7 @@ int cube_set_variant(cube_sim* sim, const cube_variant* v) {
   else if (std::find(ok.begin(), ok.end(), v->fft_col_width) == ok.end())
     err = "unsupported FFT column width for this mesh size";
   else if (v->fft_z_order < 0 || v->fft_z_order > 1) err = "fft_z_order must be 0 or 1";
-  else if (v->deposit_variant < 0 || v->deposit_variant > 7) err = "deposit_variant must be in 0..7";
+  else if (v->deposit_variant < 0 || v->deposit_variant > 3) err = "deposit_variant must be in 0..3";
   else if (v->fft_z_layout < 0 || v->fft_z_layout > 1) err = "fft_z_layout must be 0 or 1";
   else if (std::find(ok.begin(), ok.end(), v->fft_z_width) == ok.end() || v->fft_col_width % v->fft_z_width != 0)
     err = "fft_z_width must be a supported width dividing fft_col_width";

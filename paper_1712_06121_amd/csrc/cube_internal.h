@@ -63,6 +63,16 @@ struct FFTPlan {
   size_t row_floats() const { return (size_t)pitch_c * 2; }
 };
 
+// ---- two-level force: the coarse-mesh term of the Poisson solve -------------------------------
+struct CoarseTerm {
+  const float2* spec = nullptr;   // coarse density spectrum in the coarse plan's layout (null: none)
+  int64_t pitch_c = 0;            // complex values per coarse row
+  int half = 0;                   // N_c / 2
+  float rs2 = 0.0f;               // r_s^2, fine cells^2
+  float scale = 0.0f;             // R^3
+  const float2* inv_b = nullptr;  // 1 / B(f) for the signed coarse frequencies f + N_c/2, |f| < N_c/2
+};
+
 // ---- simulation ------------------------------------------------------------------------------
 struct Sim {
   cube_params p{};
@@ -122,6 +132,13 @@ struct Sim {
   int vm = 255;
   int ic_parent_np = 0;  // initial conditions refined from an ic_parent_np^3 parent (0: none)
 
+  // two-level force (cube_set_two_level): split radius r_s in fine cells (0: single-level solve),
+  // coarse FFT plan (size nc), coarse density / spectrum buffer, inverse restriction transfer
+  double two_level_rs = 0.0;
+  FFTPlan coarse_plan;
+  float* coarse = nullptr;
+  float2* inv_b = nullptr;
+
   // power spectrum accumulators
   double* pk_acc = nullptr;  // 5 x (nm/2 + 1): auto (3 rows) or cross (5 rows) shell sums
 
@@ -134,7 +151,8 @@ struct Sim {
   int steps_done = 0;
   bool half_drift_done = false;
   int move_variant = 0;     // move passes: -1 by particle density, 0 per-corner gradient, 1 gradient tile
-  int deposit_variant = 3;  // bit 0: interleaved particle order, bit 1: 512-thread workgroups
+  int deposit_variant = 3;  // bit 0: interleaved particle order, bit 1: 512-thread workgroups, bit 2: grouped cells
+  std::string autotune_report;  // per-variant times of the last cube_autotune
   double a_now = 0.0;
   bool have_particles = false;
 
@@ -181,7 +199,14 @@ void fft_plan_create(Sim& s, FFTPlan& pl, int n);
 void fft_plan_destroy(Sim& s, FFTPlan& pl);
 void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st);
 // evs (optional): 6 events recorded before the first pass and after each of the five passes
-void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs = nullptr);
+void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs = nullptr,
+                       const CoarseTerm* ct = nullptr);
+// sizes the coarse mesh of the two-level force may have (the FFT sizes and 16)
+bool fft_coarse_size_supported(int n);
+// tent-weight restriction of the fine mesh (plan fp) to the coarse mesh (plan cp, real layout)
+void launch_restrict(const FFTPlan& fp, const float* mesh, const FFTPlan& cp, float* out, hipStream_t st);
+// the Poisson solve of a step on the mesh: single-level, or two-level when switched on (api.cpp)
+void solve_potential(Sim& s, hipStream_t st, hipEvent_t* evs = nullptr);
 void fft_power(const FFTPlan& pl, float* data, double* acc, hipStream_t st);
 // the modes with every |n_i| < np/2 of the forward-transformed field src (plan ps, size np) into
 // dst (plan pd, a larger size), scaled

@@ -289,6 +289,7 @@ struct ColArgs {
   int dim;           // initial-condition component
   int half;          // N / 2
   int order;         // workgroup order: 0 dispatch order, 1 XCD-contiguous ranges
+  CoarseTerm ct;     // two-level force: the coarse-mesh term of the Poisson solve (ct.spec null: none)
 };
 
 __device__ __forceinline__ int signed_freq(int t, int n) { return t <= n / 2 ? t : t - n; }
@@ -351,13 +352,42 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
   if constexpr (MODE == COL_GREEN) {
     // z pass: t = z frequency index, column x_c = cb*BX + b, o = y index
     const float ky2 = a.k2[o];
-    for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
-      const int t = i / BX, b = i % BX;
-      const int xc = cb * BX + b;
-      const float kk = a.k2[xc] + ky2 + a.k2[t];
-      const float g = (xc == 0 && o == 0 && t == 0) ? 0.0f : a.gconst / kk;
-      const float2 v = lds[i];
-      lds[i] = make_float2(v.x * g, v.y * g);
+    if (!a.ct.spec) {
+      for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
+        const int t = i / BX, b = i % BX;
+        const int xc = cb * BX + b;
+        const float kk = a.k2[xc] + ky2 + a.k2[t];
+        const float g = (xc == 0 && o == 0 && t == 0) ? 0.0f : a.gconst / kk;
+        const float2 v = lds[i];
+        lds[i] = make_float2(v.x * g, v.y * g);
+      }
+    } else {
+      // two-level force: G [(1 - S) D_f + S R^3 D_c / B] on the modes with every |n_i| < N_c / 2,
+      // G (1 - S) D_f elsewhere; S = exp(-k^2 r_s^2), D_c the coarse density's spectrum and 1/B the
+      // restriction's inverse transfer per axis (a table over the signed coarse frequencies)
+      const CoarseTerm& c = a.ct;
+      const int fy = signed_freq(o, N);
+      const bool ylow = fy > -c.half && fy < c.half;
+      const int yc = fy < 0 ? fy + 2 * c.half : fy;
+      for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
+        const int t = i / BX, b = i % BX;
+        const int xc = cb * BX + b;
+        const float kk = a.k2[xc] + ky2 + a.k2[t];
+        const float g = (xc == 0 && o == 0 && t == 0) ? 0.0f : a.gconst / kk;
+        const float s = expf(-kk * c.rs2);
+        const float2 v = lds[i];
+        float2 r = make_float2(v.x * (1.0f - s), v.y * (1.0f - s));
+        const int fz = signed_freq(t, N);
+        if (ylow && fz > -c.half && fz < c.half && xc < c.half) {
+          const int zc = fz < 0 ? fz + 2 * c.half : fz;
+          const float2 dc = c.spec[((int64_t)zc * (2 * c.half) + yc) * c.pitch_c + xc];
+          const float2 bt = cmul(cmul(c.inv_b[fz + c.half], c.inv_b[fy + c.half]), c.inv_b[xc + c.half]);
+          const float2 u = cmul(dc, bt);
+          const float sc = s * c.scale;
+          r = make_float2(r.x + sc * u.x, r.y + sc * u.y);
+        }
+        lds[i] = make_float2(r.x * g, r.y * g);
+      }
     }
     __syncthreads();
   }
@@ -489,8 +519,8 @@ void run_col(const FFTPlan& pl, const float* src, float* dst, int axis, const Co
 }
 
 template <int N>
-void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st, hipEvent_t* ev) {
-  ColArgs a{pl.k2, gconst, nullptr, nullptr, 0, N / 2, 0};
+void solve_n(const FFTPlan& pl, float* d, float gconst, hipStream_t st, hipEvent_t* ev, const CoarseTerm* ct) {
+  ColArgs a{pl.k2, gconst, nullptr, nullptr, 0, N / 2, 0, ct ? *ct : CoarseTerm{}};
   if (ev) CUBE_HIP(hipEventRecord(ev[0], st));
   run_x<N>(pl, d, true, st);
   if (ev) CUBE_HIP(hipEventRecord(ev[1], st));
@@ -540,6 +570,7 @@ void ic_n(const FFTPlan& pl, const float* wk, float* out, const float* tab, int 
 
 #define CUBE_FFT_DISPATCH(n, CALL)                        \
   switch (n) {                                            \
+    case 16: CALL(16); break;                             \
     case 32: CALL(32); break;                             \
     case 48: CALL(48); break;                             \
     case 64: CALL(64); break;                             \
@@ -653,6 +684,101 @@ void splice_modes(const FFTPlan& ps, const float* src, const FFTPlan& pd, float*
   CUBE_HIP(hipGetLastError());
 }
 
+bool fft_coarse_size_supported(int n) { return n == 16 || fft_size_supported(n); }
+
+// ---- restriction to the coarse mesh (two-level force) ------------------------------------------
+// Tent weights (1, 3, 5, 7, 7, 5, 3, 1) / 32 over the fine offsets -2 .. 5 from a coarse cell's first
+// fine cell along each axis (the fine cells whose centres lie within 4 fine cells of the coarse
+// cell's centre, weight 1 - d / 4), summed in that order along x, then y, then z. A workgroup owns
+// 8 x 8 coarse columns and a chunk of coarse layers and walks the fine planes along z: each plane
+// is restricted along x and y into 64 values kept in a ring of 8 planes, and every fourth plane
+// completes a coarse layer. The next plane's values are requested before the current one is used.
+namespace {
+constexpr int RT = 8;           // coarse cells per column side
+constexpr int RF = 4 * RT + 4;  // fine cells per side of a loaded plane (offsets -2 .. 4 RT + 1)
+constexpr int RBLK = 256;
+constexpr int RLD = (RF * RF + RBLK - 1) / RBLK;
+
+__device__ __forceinline__ int wrapn(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__global__ __launch_bounds__(RBLK) void k_restrict(const float* __restrict__ mesh, int64_t pitch_f, int nm, int nc,
+                                                   int zc, float* __restrict__ out, int64_t opitch_f) {
+  __shared__ float plane[RF * RF];
+  __shared__ float xr[RF * RT];
+  __shared__ float ring[8 * RT * RT];
+  constexpr float w[8] = {0.03125f, 0.09375f, 0.15625f, 0.21875f, 0.21875f, 0.15625f, 0.09375f, 0.03125f};
+  const int ncol = nc / RT;
+  const unsigned lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int bxy = (int)(lb % gridDim.x), bz = (int)(lb / gridDim.x);
+  const int cx0 = (bxy % ncol) * RT, cy0 = (bxy / ncol) * RT;
+  const int cz0 = bz * zc, cz1 = min(cz0 + zc, nc);
+  const int fx0 = 4 * cx0 - 2, fy0 = 4 * cy0 - 2;
+  int col[RLD];
+  int64_t row[RLD];
+#pragma unroll
+  for (int k = 0; k < RLD; ++k) {
+    const int i = threadIdx.x + k * RBLK;
+    const int y = i / RF, x = i - (i / RF) * RF;
+    col[k] = wrapn(fx0 + x, nm);
+    row[k] = (int64_t)wrapn(fy0 + (i < RF * RF ? y : 0), nm) * pitch_f;
+  }
+  auto fetch = [&](int fz, float* v) {
+    const float* pl = mesh + (int64_t)wrapn(fz, nm) * nm * pitch_f;
+#pragma unroll
+    for (int k = 0; k < RLD; ++k)
+      if (threadIdx.x + k * RBLK < RF * RF) v[k] = pl[row[k] + col[k]];
+  };
+  float cur[RLD], nxt[RLD];
+  const int fz_end = 4 * cz1 + 1;
+  fetch(4 * cz0 - 2, cur);
+  for (int fz = 4 * cz0 - 2; fz <= fz_end; ++fz) {
+    fetch(fz < fz_end ? fz + 1 : fz, nxt);
+#pragma unroll
+    for (int k = 0; k < RLD; ++k)
+      if (threadIdx.x + k * RBLK < RF * RF) plane[threadIdx.x + k * RBLK] = cur[k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < RF * RT; i += RBLK) {
+      const int y = i / RT, c = i - (i / RT) * RT;
+      float acc = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc += w[b] * plane[y * RF + 4 * c + b];
+      xr[i] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < RT * RT) {
+      const int cy = threadIdx.x / RT, cx = threadIdx.x % RT;
+      float acc = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc += w[b] * xr[(4 * cy + b) * RT + cx];
+      ring[(fz & 7) * RT * RT + threadIdx.x] = acc;
+    }
+    __syncthreads();
+    // coarse layer c is complete once plane 4 c + 5 is in the ring (planes 4 c - 2 .. 4 c + 5)
+    if (((fz - 5) & 3) == 0 && fz >= 4 * cz0 + 5 && threadIdx.x < RT * RT) {
+      const int c = (fz - 5) / 4;
+      float acc = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) acc += w[b] * ring[((4 * c - 2 + b) & 7) * RT * RT + threadIdx.x];
+      out[((int64_t)c * nc + cy0 + threadIdx.x / RT) * opitch_f + cx0 + threadIdx.x % RT] = acc;
+    }
+#pragma unroll
+    for (int k = 0; k < RLD; ++k) cur[k] = nxt[k];
+  }
+}
+}  // namespace
+
+void launch_restrict(const FFTPlan& fp, const float* mesh, const FFTPlan& cp, float* out, hipStream_t st) {
+  const int nc = cp.n, nm = fp.n;
+  const int cols = (nc / RT) * (nc / RT);
+  int nchunk = 16384 / cols;
+  nchunk = nchunk < 1 ? 1 : (nchunk > nc ? nc : nchunk);
+  const int zc = (nc + nchunk - 1) / nchunk;
+  nchunk = (nc + zc - 1) / zc;
+  const dim3 grid((unsigned)cols, (unsigned)nchunk);
+  k_restrict<<<grid, RBLK, 0, st>>>(mesh, (int64_t)fp.row_floats(), nm, nc, zc, out, (int64_t)cp.row_floats());
+  CUBE_HIP(hipGetLastError());
+}
+
 bool fft_size_supported(int n) {
   switch (n) {
     case 32: case 48: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 1024: case 2048:
@@ -697,8 +823,9 @@ void fft_plan_destroy(Sim& s, FFTPlan& pl) {
   pl.k2 = nullptr;
 }
 
-void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs) {
-#define CUBE_CALL(N) solve_n<N>(pl, data, gconst, st, evs)
+void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t st, hipEvent_t* evs,
+                       const CoarseTerm* ct) {
+#define CUBE_CALL(N) solve_n<N>(pl, data, gconst, st, evs, ct)
   CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
 #undef CUBE_CALL
 }

@@ -357,269 +357,6 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   }
 }
 
-// Deposit with the source cells of a layer in three groups: the 36 interior cells of the column
-// (their CIC corners always fall inside it), the 28 other own cells, and the 36 ring cells, of
-// whose particles only those within half a fine cell of the column reach it. A wavefront takes 64
-// consecutive particles of a group; a lane's source cell follows from the group's prefix counts
-// by a forward walk shared by the wavefront. Interior particles of the layers whose planes all
-// belong to the workgroup deposit with no bounds tests. Ring particles are first tested, and the
-// ones that reach the column are packed into a queue held one per lane (a permutation of the
-// lanes, no LDS memory) that is deposited once 64 have gathered. The sums are exact integers, so
-// the order of the additions does not matter: the density is that of k_deposit, bit for bit.
-constexpr int DQ_INT = 36;   // interior own cells (x, y in 1..6)
-constexpr int DQ_OWN = 64;   // own cells
-__device__ __forceinline__ void dq_cell(int e, int& sx, int& sy) {
-  if (e < DQ_INT) {
-    sx = 1 + e % 6;
-    sy = 1 + e / 6;
-  } else if (e < DQ_OWN) {
-    const int b = e - DQ_INT;  // rows y = 0 and 7, then columns x = 0 and 7 for y in 1..6
-    if (b < 8) { sx = b; sy = 0; }
-    else if (b < 16) { sx = b - 8; sy = 7; }
-    else if (b < 22) { sx = 0; sy = b - 15; }
-    else { sx = 7; sy = b - 21; }
-  } else {
-    const int r = e - DQ_OWN;  // ring: rows y = -1 and 8 (x in -1..8), then columns x = -1 and 8 (y in 0..7)
-    if (r < 10) { sx = r - 1; sy = -1; }
-    else if (r < 20) { sx = r - 11; sy = 8; }
-    else if (r < 28) { sx = -1; sy = r - 20; }
-    else { sx = 8; sy = r - 28; }
-  }
-}
-
-template <int NCHI, int BLK>
-__global__ __launch_bounds__(BLK) void k_deposit_q(DepArgs a) {
-  using CT = chi_t<NCHI>;
-  constexpr int SH = 8 * NCHI - 1;
-  constexpr int NW = BLK / 64;
-  __shared__ unsigned long long rho[NSLOT * DF * DF];
-  __shared__ uint32_t pre[DRC + 1];
-  __shared__ uint64_t start[DRC];
-  __shared__ uint8_t sxy[DRC];  // (sx + 1) | (sy + 1) << 4 of each entry
-  __shared__ uint32_t wsum[NW];
-  __shared__ uint32_t smax;
-  const unsigned lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const unsigned bxy = lb % gridDim.x, bz = lb / gridDim.x;
-  const int cx0 = (bxy % a.nt) * DTX, cy0 = (bxy / a.nt) * DTX;
-  const int cz0 = bz * a.zc;
-  const int cz1 = min(cz0 + a.zc, a.nc);
-  const int pz0 = 4 * cz0, pz1 = 4 * cz1;  // owned fine planes [pz0, pz1)
-  for (int i = threadIdx.x; i < NSLOT * DF * DF; i += BLK) rho[i] = 0ull;
-  if (threadIdx.x == 0) smax = 0u;
-  if (threadIdx.x < DRC) {
-    int sx, sy;
-    dq_cell(threadIdx.x, sx, sy);
-    sxy[threadIdx.x] = (uint8_t)((sx + 1) | ((sy + 1) << 4));
-  }
-  __syncthreads();
-  // 32-bit accumulators when every source cell holds at most 255 particles (1-byte codes): a fine
-  // cell then receives less than 8 * 255 * 2^21 < 2^32
-  if constexpr (NCHI == 1) {
-    uint32_t m = 0u;
-    const int ncell = DRC * (cz1 - cz0 + 2);
-    for (int i = threadIdx.x; i < ncell; i += BLK) {
-      const int t = i % DRC, sz = cz0 - 1 + i / DRC;
-      const int sx = t % DR - 1, sy = t / DR - 1;
-      const uint32_t c = a.cnt[wrapi(cx0 + sx, a.nc) + (int64_t)a.nc * (wrapi(cy0 + sy, a.nc) + (int64_t)a.nc * wrapi(sz, a.nc))];
-      m = c > m ? c : m;
-    }
-    atomicMax(&smax, m);
-  }
-  __syncthreads();
-  const bool narrow = NCHI == 1 && smax <= 255u;
-  uint32_t* rho32 = reinterpret_cast<uint32_t*>(rho);
-  const CT* cx = static_cast<const CT*>(a.chi);
-  const CT* cy = cx + a.cap;
-  const CT* cz = cy + a.cap;
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  for (int sz = cz0 - 1; sz <= cz1; ++sz) {
-    uint32_t cntv = 0;
-    if (threadIdx.x < DRC) {
-      const int sx = (sxy[threadIdx.x] & 15) - 1, sy = (sxy[threadIdx.x] >> 4) - 1;
-      const int64_t c = wrapi(cx0 + sx, a.nc) + (int64_t)a.nc * (wrapi(cy0 + sy, a.nc) + (int64_t)a.nc * wrapi(sz, a.nc));
-      cntv = a.cnt[c];
-      start[threadIdx.x] = a.off[c];
-    }
-    block_exclusive_scan(cntv, pre, DRC, wsum);  // ends with a barrier
-    // slot of plane 4 sz - 1 + r for r in 0..5 (the planes this layer touches): (s0 + r) mod 6
-    const int s0 = slot_of(4 * sz - 1);
-    // the layer's planes all belong to the workgroup: no z tests
-    const bool zin = 4 * sz - 1 >= pz0 && 4 * sz + 4 < pz1;
-    auto run = [&](auto* acc) {
-      using A = typename std::remove_pointer<decltype(acc)>::type;
-      // CIC of one particle of source cell (sx, sy) with codes ch; CXY / CZ: test the corners
-      auto deposit = [&](auto cxy, auto cz_, const int sx, const int sy, const int* ch) {
-        constexpr bool CXY = decltype(cxy)::value, CZ = decltype(cz_)::value;
-        const int sl[3] = {sx, sy, sz};
-        int i0[3], w1[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const int pl = sl[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
-          i0[d] = pl >> SH;
-          w1[d] = pl & ((1 << SH) - 1);
-        }
-        const uint32_t wz2[2] = {(uint32_t)((1 << SH) - w1[2]), (uint32_t)w1[2]};
-        const uint32_t wy2[2] = {(uint32_t)((1 << SH) - w1[1]), (uint32_t)w1[1]};
-        const uint32_t wx2[2] = {(uint32_t)((1 << SH) - w1[0]), (uint32_t)w1[0]};
-        const int r = i0[2] - (4 * sz - 1);  // 0 .. 4
-        const int sa = s0 + r >= NSLOT ? s0 + r - NSLOT : s0 + r;
-        const int sb = sa + 1 == NSLOT ? 0 : sa + 1;
-        const int slot2[2] = {sa * DF * DF, sb * DF * DF};
-        const int base = i0[1] * DF + i0[0];
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz) {
-          if (CZ) {
-            const int pz = i0[2] + dz;
-            if (pz < pz0 || pz >= pz1) continue;
-          }
-#pragma unroll
-          for (int dy = 0; dy < 2; ++dy) {
-            if (CXY) {
-              const int y = i0[1] + dy;
-              if (y < 0 || y >= DF) continue;
-            }
-            const uint32_t wzy = wz2[dz] * wy2[dy];
-#pragma unroll
-            for (int dx = 0; dx < 2; ++dx) {
-              if (CXY) {
-                const int x = i0[0] + dx;
-                if (x < 0 || x >= DF) continue;
-              }
-              const A w = NCHI == 1 ? (A)(wzy * wx2[dx]) : (A)((unsigned long long)wzy * (unsigned long long)wx2[dx]);
-              atomicAdd(&acc[slot2[dz] + base + dy * DF + dx], w);
-            }
-          }
-        }
-      };
-      using T_ = std::true_type;
-      using F_ = std::false_type;
-      // entries [e0, e1): particles [pre[e0], pre[e1]) in windows of 64 per wavefront; body(i, act, e, p)
-      auto windows = [&](int e0, int e1, auto&& body) {
-        const uint32_t q0 = pre[e0], q1 = pre[e1];
-        int ec = e0;  // the cell of the window's first particle (wave-uniform, non-decreasing)
-        for (uint32_t w0 = q0 + 64u * (uint32_t)wave; w0 < q1; w0 += BLK) {
-          while ((uint32_t)__builtin_amdgcn_readfirstlane(pre[ec + 1]) <= w0) ++ec;
-          const uint32_t i = w0 + (uint32_t)lane;
-          int e = ec;
-          for (int k = ec + 1; k < e1; ++k) {
-            const uint32_t pk = (uint32_t)__builtin_amdgcn_readfirstlane(pre[k]);
-            if (pk >= w0 + 64u) break;
-            if (pk <= i) e = k;
-          }
-          const bool act = i < q1;
-          // lanes past the end read the window's first particle (cell ec holds it)
-          const int64_t p = act ? (int64_t)start[e] + (i - pre[e]) : (int64_t)start[ec] + (w0 - pre[ec]);
-          body(act, e, p);
-        }
-      };
-      auto load = [&](int64_t p, int* ch) {
-        ch[0] = (int)cx[p];
-        ch[1] = (int)cy[p];
-        ch[2] = (int)cz[p];
-      };
-      // interior own cells: no x/y tests (and no z tests for the layers inside the chunk)
-      windows(0, DQ_INT, [&](bool act, int e, int64_t p) {
-        int ch[3];
-        load(p, ch);
-        if (act) {
-          const int sx = (sxy[e] & 15) - 1, sy = (sxy[e] >> 4) - 1;
-          if (zin) deposit(F_{}, F_{}, sx, sy, ch);
-          else deposit(F_{}, T_{}, sx, sy, ch);
-        }
-      });
-      windows(DQ_INT, DQ_OWN, [&](bool act, int e, int64_t p) {
-        int ch[3];
-        load(p, ch);
-        if (act) {
-          const int sx = (sxy[e] & 15) - 1, sy = (sxy[e] >> 4) - 1;
-          if (zin) deposit(T_{}, F_{}, sx, sy, ch);
-          else deposit(T_{}, T_{}, sx, sy, ch);
-        }
-      });
-      // ring: the particles whose CIC cloud reaches the column, gathered into full wavefronts
-      uint32_t qa = 0u, qb = 0u;  // queue entry of this lane: sxy | codes (two words for 2-byte codes)
-      uint32_t qn = 0u;           // entries in lanes [0, qn) (wave-uniform)
-      auto unpack_deposit = [&](uint32_t wa, uint32_t wb) {
-        int ch[3];
-        if constexpr (NCHI == 1) {
-          ch[0] = (int)((wa >> 8) & 255u);
-          ch[1] = (int)((wa >> 16) & 255u);
-          ch[2] = (int)(wa >> 24);
-        } else {
-          ch[0] = (int)(wa >> 16);
-          ch[1] = (int)(wb & 65535u);
-          ch[2] = (int)(wb >> 16);
-        }
-        const int sx = (int)(wa & 15u) - 1, sy = (int)((wa >> 4) & 15u) - 1;
-        deposit(T_{}, T_{}, sx, sy, ch);
-      };
-      windows(DQ_OWN, DRC, [&](bool act, int e, int64_t p) {
-        int ch[3];
-        load(p, ch);
-        const uint32_t code = sxy[e];
-        const int sx = (int)(code & 15u) - 1, sy = (int)(code >> 4) - 1;
-        const int ix = (sx * (1 << (SH + 2)) + 2 * ch[0] + 1 - (1 << (SH - 1))) >> SH;
-        const int iy = (sy * (1 << (SH + 2)) + 2 * ch[1] + 1 - (1 << (SH - 1))) >> SH;
-        const int iz = (sz * (1 << (SH + 2)) + 2 * ch[2] + 1 - (1 << (SH - 1))) >> SH;
-        const bool take = act && ix >= -1 && ix < DF && iy >= -1 && iy < DF && iz + 1 >= pz0 && iz < pz1;
-        uint32_t wa, wb = 0u;
-        if constexpr (NCHI == 1) {
-          wa = code | ((uint32_t)ch[0] << 8) | ((uint32_t)ch[1] << 16) | ((uint32_t)ch[2] << 24);
-        } else {
-          wa = code | ((uint32_t)ch[0] << 16);
-          wb = (uint32_t)ch[1] | ((uint32_t)ch[2] << 16);
-        }
-        // the taken lanes to lanes [0, c) in lane order, the others after them: a permutation
-        const unsigned long long m = __ballot(take);
-        const uint32_t c = (uint32_t)__popcll(m);
-        const uint32_t dst = take ? lanes_below(m) : c + lanes_below(~m);
-        wa = (uint32_t)__builtin_amdgcn_ds_permute((int)(dst * 4u), (int)wa);
-        if constexpr (NCHI == 2) wb = (uint32_t)__builtin_amdgcn_ds_permute((int)(dst * 4u), (int)wb);
-        // behind the qn queued entries: lane j takes the gathered entry j - qn
-        const int src = (int)(((uint32_t)lane - qn) & 63u) * 4;
-        const uint32_t ra = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)wa);
-        const uint32_t rb = NCHI == 2 ? (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)wb) : 0u;
-        if (qn + c < 64u) {
-          if ((uint32_t)lane >= qn && (uint32_t)lane < qn + c) {
-            qa = ra;
-            qb = rb;
-          }
-          qn += c;
-        } else {
-          const uint32_t fa = (uint32_t)lane < qn ? qa : ra, fb = (uint32_t)lane < qn ? qb : rb;
-          unpack_deposit(fa, fb);
-          qa = ra;
-          qb = rb;
-          qn = qn + c - 64u;
-        }
-      });
-      if ((uint32_t)lane < qn) unpack_deposit(qa, qb);
-    };
-    if (narrow) run(rho32);
-    else run(rho);
-    __syncthreads();
-    // planes completed by this layer
-    const int f0 = max(4 * sz - 1, pz0), f1 = min(4 * sz + 2, pz1 - 1);
-    const int nplanes = f1 - f0 + 1;
-    for (int i = threadIdx.x; i < nplanes * DF * DF; i += BLK) {
-      const int pz = f0 + i / (DF * DF), e = i % (DF * DF);
-      const int y = e / DF, x = e - y * DF;
-      const int idx = slot_of(pz) * DF * DF + e;
-      double r;
-      if (narrow) {
-        r = (double)rho32[idx];
-        rho32[idx] = 0u;
-      } else {
-        r = (double)rho[idx];
-        rho[idx] = 0ull;
-      }
-      a.mesh[((int64_t)pz * a.nm + (4 * cy0 + y)) * a.pitch_f + (4 * cx0 + x)] = (float)(r * a.inv_mean - 1.0);
-    }
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------------------------------------
 // Move passes. MODE 0: kick with the potential in the mesh + drift; MODE 1: drift only;
 // MODE 2: initial conditions (lattice + Zel'dovich displacement).
@@ -1378,152 +1115,210 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   const float unit = (float)(1.0 / (double)(1 << SH));
   CT* chi_n = static_cast<CT*>(a.chi_n);
   NT* nu_n = static_cast<NT*>(a.nu_n);
-  // Each wave takes one row of T cells along x (16 rows, 16 waves): their particles are contiguous
-  // in storage, so the wave's chunks of 64 lanes stay full across cell boundaries. A lane's cell in
-  // the row follows from the row's prefix counts.
-  static_assert(T == 4 && TC / T == NTH / 64, "one row of four cells per wave");
-  {
-    const int row = wave;
-    const int s0 = T * row, o1 = row % T, o2 = row / T;
-    const uint32_t p1 = pre[s0 + 1] - pre[s0], p2 = pre[s0 + 2] - pre[s0], p3 = pre[s0 + 3] - pre[s0];
-    const uint32_t nrow = pre[s0 + 4] - pre[s0];
-    const uint64_t base = start[s0];
-    const CT* chx = static_cast<const CT*>(a.chi) + base;
-    const NT* nux = static_cast<const NT*>(a.nu) + base;
-    const int64_t crow = (int64_t)a.nc * ((g.cy0 + o1) + (int64_t)a.nc * (g.cz0 + o2));
-    // the codes of the next chunk are loaded before this chunk's atomics and stores are issued, so
-    // waiting for them never waits for those (the vector memory counter is in order)
-    // unconditional loads (past the row's end they repeat its last particle, whose codes go
-    // unused), so that the number of memory operations issued after them does not depend on the
-    // path and the wait for them does not also wait for this chunk's stores and atomics
-    int chn[3] = {0, 0, 0}, nun[3] = {0, 0, 0};
-    auto load_chunk = [&](uint32_t jj) {
-      jj = min(jj, nrow - 1);
+  // kick, drift, new cell and code of one particle (cell s at tile offsets (ci, o1, o2), codes chc,
+  // nuc); inactive lanes keep v = l = 0
+  auto physics = [&](bool active, int s, int ci, int o1, int o2, const int* chc, const int* nuc, float* v, int* k,
+                     int* cq) {
+    float l[3] = {0.f, 0.f, 0.f};
+    v[0] = v[1] = v[2] = 0.f;
+    float vv = 0.f, tq = 0.f;
+    int ch[3] = {0, 0, 0};
+    if (active) {
+      const float4 cv = cellv[s];
+      const float vcv[3] = {cv.x, cv.y, cv.z};
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        chn[d] = (int)chx[d * a.cap + jj];
-        nun[d] = (int)nux[d * a.cap + jj];
+        ch[d] = chc[d];
+        int nuv = nuc[d];
+        nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
+        l[d] = (float)(2 * ch[d] + 1) * unit;
+        v[d] = __builtin_fmaf(cv.w, tdec[nuv + a.vhalf], vcv[d]);
+      }
+      // CIC corners relative to the tile, exact dyadic weights, interpolated gradient
+      const int o[3] = {ci, o1, o2};
+      int i0[3];
+      float w0[3], w1[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
+        i0[d] = pl >> SH;
+        const int f = pl & ((1 << SH) - 1);
+        w1[d] = (float)f * unit;
+        w0[d] = 1.0f - w1[d];  // exact: both are multiples of 2^-SH in [0, 1]
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        float sacc[2];
+#pragma unroll
+        for (int cz = 0; cz < 2; ++cz) {
+          float racc[2];
+#pragma unroll
+          for (int cy = 0; cy < 2; ++cy) {
+            const float d0 = grad_at<true>(ph, gd, d, i0[0], i0[1] + cy, i0[2] + cz);
+            const float d1 = grad_at<true>(ph, gd, d, i0[0] + 1, i0[1] + cy, i0[2] + cz);
+            racc[cy] = __builtin_fmaf(w1[0], d1, w0[0] * d0);
+          }
+          sacc[cz] = __builtin_fmaf(w1[1], racc[1], w0[1] * racc[0]);
+        }
+        const float t = __builtin_fmaf(w1[2], sacc[1], w0[2] * sacc[0]);
+        v[d] = __builtin_fmaf(t, a.kf, v[d]);
+        if constexpr (MEAS) tq = d == 0 ? t * t : tq + t * t;
+      }
+      if constexpr (MEAS) vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) l[d] = __builtin_fmaf(v[d], a.df, l[d]);
+    }
+    if constexpr (MEAS) raise_maxima(a.amax, vv, tq);
+    // new cell, codes, flags (same rules as the generic path)
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      if (!new_cell<SH>(l[d], v[d], a.flags, k[d], cq[d])) ok = false;
+    if (!ok) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = 0.0f;
+    }
+  };
+  if constexpr (!SCATTER) {
+    // Count pass: the wavefronts take every NW-th chunk of 64 of the tile's particles (its 64 cells in
+    // storage order, one after the other), so that a crowded cell is shared by all of them; the lanes
+    // of a chunk find their cells from the prefix counts by a forward walk shared by the wavefront.
+    constexpr int NW = NTH / 64;
+    const uint32_t tot = pre[TC];
+    const CT* chx = static_cast<const CT*>(a.chi);
+    const NT* nux = static_cast<const NT*>(a.nu);
+    int ec = 0;  // the cell of the chunk's first particle (wave-uniform, non-decreasing)
+    auto locate = [&](uint32_t c0, int& sc, int64_t& p) {
+      while ((uint32_t)__builtin_amdgcn_readfirstlane(pre[ec + 1]) <= c0) ++ec;
+      const uint32_t i = c0 + (uint32_t)lane;
+      sc = ec;
+      for (int q = ec + 1; q < TC; ++q) {
+        const uint32_t pq = (uint32_t)__builtin_amdgcn_readfirstlane(pre[q]);
+        if (pq >= c0 + 64u) break;
+        if (pq <= i) sc = q;
+      }
+      // lanes past the end read the chunk's first particle
+      p = i < tot ? (int64_t)start[sc] + (i - pre[sc]) : (int64_t)start[ec] + (c0 - pre[ec]);
+    };
+    int chn[3] = {0, 0, 0}, nun[3] = {0, 0, 0};
+    auto load_at = [&](int64_t p) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        chn[d] = (int)chx[d * a.cap + p];
+        nun[d] = (int)nux[d * a.cap + p];
       }
     };
-    if (nrow > 0) load_chunk(lane);
-    uint32_t scnt[T] = {0u, 0u, 0u, 0u};  // scatter: stayers ranked so far per cell of the row
-    for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
-      const uint32_t j = j0 + lane;
-      const bool active = j < nrow;
-      const int ci = (int)(j >= p1) + (int)(j >= p2) + (int)(j >= p3);  // cell of the row
-      const int s = s0 + ci;
+    uint32_t c0 = 64u * (uint32_t)wave;
+    int sn = 0;
+    int64_t pn = 0;
+    if (c0 < tot) {
+      locate(c0, sn, pn);
+      load_at(pn);
+    }
+    for (; c0 < tot; c0 += 64u * NW) {
+      const uint32_t i = c0 + (uint32_t)lane;
+      const bool active = i < tot;
+      const int s = sn;
       const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
-      load_chunk(j + 64);
-      float v[3] = {0.f, 0.f, 0.f}, l[3] = {0.f, 0.f, 0.f};
-      float vv = 0.f, tq = 0.f;
-      int ch[3] = {0, 0, 0};
-      if (active) {
-        const float4 cv = cellv[s];
-        const float vcv[3] = {cv.x, cv.y, cv.z};
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          ch[d] = chc[d];
-          int nuv = nuc[d];
-          nuv = nuv < -a.vhalf ? -a.vhalf : (nuv > a.vhalf ? a.vhalf : nuv);
-          l[d] = (float)(2 * ch[d] + 1) * unit;
-          v[d] = __builtin_fmaf(cv.w, tdec[nuv + a.vhalf], vcv[d]);
-        }
-        // CIC corners relative to the tile, exact dyadic weights, interpolated gradient
-        const int o[3] = {ci, o1, o2};
-        int i0[3];
-        float w0[3], w1[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const int pl = o[d] * (1 << (SH + 2)) + 2 * ch[d] + 1 - (1 << (SH - 1));
-          i0[d] = pl >> SH;
-          const int f = pl & ((1 << SH) - 1);
-          w1[d] = (float)f * unit;
-          w0[d] = 1.0f - w1[d];  // exact: both are multiples of 2^-SH in [0, 1]
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          float sacc[2];
-#pragma unroll
-          for (int cz = 0; cz < 2; ++cz) {
-            float racc[2];
-#pragma unroll
-            for (int cy = 0; cy < 2; ++cy) {
-              const float d0 = grad_at<true>(ph, gd, d, i0[0], i0[1] + cy, i0[2] + cz);
-              const float d1 = grad_at<true>(ph, gd, d, i0[0] + 1, i0[1] + cy, i0[2] + cz);
-              racc[cy] = __builtin_fmaf(w1[0], d1, w0[0] * d0);
-            }
-            sacc[cz] = __builtin_fmaf(w1[1], racc[1], w0[1] * racc[0]);
-          }
-          const float t = __builtin_fmaf(w1[2], sacc[1], w0[2] * sacc[0]);
-          v[d] = __builtin_fmaf(t, a.kf, v[d]);
-          if constexpr (MEAS) tq = d == 0 ? t * t : tq + t * t;
-        }
-        if constexpr (MEAS) vv = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) l[d] = __builtin_fmaf(v[d], a.df, l[d]);
-      }
-      if constexpr (MEAS) raise_maxima(a.amax, vv, tq);
-      // new cell, codes, flags (same rules as the generic path)
+      // the codes of the next chunk are requested before this chunk's atomics are issued (past the
+      // end the request repeats a particle of this chunk)
+      if (c0 + 64u * NW < tot) locate(c0 + 64u * NW, sn, pn);
+      load_at(pn);
+      const int ci = s % T, o1 = (s / T) % T, o2 = s / (T * T);
+      float v[3];
       int k[3], cq[3];
-      bool ok = true;
-#pragma unroll
-      for (int d = 0; d < 3; ++d)
-        if (!new_cell<SH>(l[d], v[d], a.flags, k[d], cq[d])) ok = false;
-      if (!ok) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = 0.0f;
-      }
+      physics(active, s, ci, o1, o2, chc, nuc, v, k, cq);
       const int dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1);
-      if constexpr (!SCATTER) {
-        long long q[4];
-        velocity_moments(v, q);  // inactive lanes hold v = 0
-        const bool stay = active && dcode == 13;
-        const unsigned long long smask = __ballot(stay);
-        // stayers: one prefix sum over the chunk, then the difference over each cell's lanes
-        unsigned long long ps[4];
+      const uint32_t cbeg = pre[s], cend = pre[s + 1];
+      const uint32_t j0 = c0, j = i;
+      long long q[4];
+      velocity_moments(v, q);  // inactive lanes hold v = 0
+      const bool stay = active && dcode == 13;
+      const unsigned long long smask = __ballot(stay);
+      // stayers: one prefix sum over the chunk, then the difference over each cell's lanes
+      unsigned long long ps[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) ps[d] = wave_scan_u64(stay ? (unsigned long long)q[d] : 0ull);
-        const int cfirst = __builtin_amdgcn_readfirstlane(ci);
-        const uint32_t jend = nrow - j0 < 64u ? nrow - j0 : 64u;  // active lanes
-        const int clast = __builtin_amdgcn_readlane(ci, (int)jend - 1);
-        const uint32_t bnd[5] = {0u, p1, p2, p3, nrow};
-        for (int cc = cfirst; cc <= clast; ++cc) {
-          const int la = (int)(bnd[cc] > j0 ? bnd[cc] - j0 : 0u);
-          const int lb = (int)((bnd[cc + 1] - j0 < jend ? bnd[cc + 1] - j0 : jend)) - 1;
-          if (la > lb) continue;
-          const unsigned long long seg = (lb == 63 ? ~0ull : ((2ull << lb) - 1ull)) & ~((1ull << la) - 1ull);
-          const int nst = __popcll(smask & seg);
-          if (nst == 0) continue;
-          unsigned long long tot[4];
+      for (int d = 0; d < 4; ++d) ps[d] = wave_scan_u64(stay ? (unsigned long long)q[d] : 0ull);
+      // The last lane of each of the chunk's cells adds the cell's stayers: their number
+      // and moment sums are the differences of the inclusive scans at that lane and at the lane
+      // before the cell's first one in the chunk (fetched with one lane shuffle per word).
+      const int la = cbeg > j0 ? (int)(cbeg - j0) : 0;  // the cell's first lane in the chunk
+      const int from = (la > 0 ? la - 1 : 0) * 4;
+      const bool tail = active && (j + 1u == cend || lane == 63);
+      const unsigned long long seg = (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)) & ~((1ull << la) - 1ull);
+      const uint32_t nst = (uint32_t)__popcll(smask & seg);
+      unsigned long long sum4[4];
 #pragma unroll
-          for (int d = 0; d < 4; ++d)
-            tot[d] = read_lane_u64(ps[d], lb) - (la > 0 ? read_lane_u64(ps[d], la - 1) : 0ull);
-          if (lane == 0) {
-            atomicAdd(&grp[(s0 + cc) * 27 + 13], (uint32_t)nst);
+      for (int d = 0; d < 4; ++d) {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)ps[d]);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(ps[d] >> 32));
+        sum4[d] = ps[d] - (la > 0 ? (((unsigned long long)hi << 32) | lo) : 0ull);
+      }
+      if (tail && nst > 0u) {
+        atomicAdd(&grp[s * 27 + 13], nst);
 #pragma unroll
-            for (int d = 0; d < 4; ++d) atomicAdd(&omom[(s0 + cc) * 4 + d], tot[d]);
+        for (int d = 0; d < 4; ++d) atomicAdd(&omom[s * 4 + d], sum4[d]);
+      }
+      if (active && !stay) {
+        atomicAdd(&grp[s * 27 + dcode], 1u);
+        // new cell inside the tile: the tile's LDS accumulators; in the ring: the global ones
+        const int tx = ci + k[0], ty = o1 + k[1], tz = o2 + k[2];
+        if (tx >= 0 && tx < T && ty >= 0 && ty < T && tz >= 0 && tz < T) {
+          const int so = tx + T * (ty + T * tz);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) atomicAdd(&omom[so * 4 + d], (unsigned long long)q[d]);
+        } else {
+          // the cell index and byte offsets fit 32 bits (nc^3 < 2^28); the plane bases are uniform
+          const uint32_t nx = (uint32_t)wrapi(g.cx0 + tx, a.nc), ny = (uint32_t)wrapi(g.cy0 + ty, a.nc);
+          const uint32_t nz = (uint32_t)wrapi(g.cz0 + tz, a.nc), ncu = (uint32_t)a.nc;
+          const uint32_t boff = (nx + ncu * (ny + ncu * nz)) * 8u;
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            char* plane = reinterpret_cast<char*>(a.mom + (int64_t)d * a.nc3);
+            atomicAdd(reinterpret_cast<unsigned long long*>(plane + boff), (unsigned long long)q[d]);
           }
         }
-        if (active && !stay) {
-          atomicAdd(&grp[s * 27 + dcode], 1u);
-          // new cell inside the tile: the tile's LDS accumulators; in the ring: the global ones
-          const int tx = ci + k[0], ty = o1 + k[1], tz = o2 + k[2];
-          if (tx >= 0 && tx < T && ty >= 0 && ty < T && tz >= 0 && tz < T) {
-            const int so = tx + T * (ty + T * tz);
+      }
+    }
+  } else {
+    // Scatter pass: each wave takes one row of T cells along x (16 rows, 16 waves); the row's
+    // particles are contiguous, so its 64-lane chunks stay full across the row's cell boundaries,
+    // and only this wave ranks particles of the row's cells.
+    for (int row = wave; row < T * T; row += NTH / 64) {
+      const int s0 = row * T, o1 = row % T, o2 = row / T;
+      const uint32_t r0 = pre[s0];
+      const uint32_t p1 = pre[s0 + 1] - r0, p2 = pre[s0 + 2] - r0, p3 = pre[s0 + 3] - r0, nrow = pre[s0 + T] - r0;
+      const int64_t base = (int64_t)start[s0];
+      const CT* chx = static_cast<const CT*>(a.chi) + base;
+      const NT* nux = static_cast<const NT*>(a.nu) + base;
+      // the next chunk's codes are requested before this chunk's stores are issued, so that waiting
+      // for them never waits for those (the vector memory counter is in order); past the row's end
+      // the request repeats its last particle, so it needs no branch
+      int chn[3] = {0, 0, 0}, nun[3] = {0, 0, 0};
+      auto load_chunk = [&](uint32_t jj) {
+        jj = min(jj, nrow - 1);
 #pragma unroll
-            for (int d = 0; d < 4; ++d) atomicAdd(&omom[so * 4 + d], (unsigned long long)q[d]);
-          } else {
-            const int nx = wrapi(g.cx0 + tx, a.nc), ny = wrapi(g.cy0 + ty, a.nc), nz = wrapi(g.cz0 + tz, a.nc);
-            const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
-#pragma unroll
-            for (int d = 0; d < 4; ++d)
-              atomicAdd(reinterpret_cast<unsigned long long*>(&a.mom[d * a.nc3 + cn]), (unsigned long long)q[d]);
-          }
+        for (int d = 0; d < 3; ++d) {
+          chn[d] = (int)chx[d * a.cap + jj];
+          nun[d] = (int)nux[d * a.cap + jj];
         }
-      } else {
-        // rank among the lanes with the same (cell of the row, displacement), in storage order;
-        // only this wave ranks particles of the row's cells. Stayers: a running count per cell of
-        // the row, kept by the wave. Movers (few): one pass per distinct key, counters in LDS.
+      };
+      if (nrow > 0) load_chunk(lane);
+      uint32_t scnt[T] = {0u, 0u, 0u, 0u};  // stayers ranked so far per cell of the row
+      for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
+        const uint32_t j = j0 + lane;
+        const bool active = j < nrow;
+        const int ci = (int)(j >= p1) + (int)(j >= p2) + (int)(j >= p3);  // cell of the row
+        const int s = s0 + ci;
+        const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
+        load_chunk(j + 64);
+        float v[3];
+        int k[3], cq[3];
+        physics(active, s, ci, o1, o2, chc, nuc, v, k, cq);
+        const int dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1);
+        // rank among the lanes with the same (cell of the row, displacement), in storage order.
+        // Stayers: a running count per cell of the row, kept by the wave. Movers (few): one pass
+        // per distinct key, counters in LDS.
         uint32_t rin = 0, gbase = 0;
         const bool stay = active && dcode == 13;
         const unsigned long long smask = __ballot(stay);
@@ -1575,7 +1370,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
               nu_n[d * a.cap + dst] = (NT)encode_nu<false>(u, edges, bucket, a.nbucket, a.vhalf);
               chi_n[d * a.cap + dst] = (CT)cq[d];
             }
-            if (a.pid_bytes) store_id(a, dst, particle_id<0>(a, g, s, (int64_t)(base + j), 0u));
+            if (a.pid_bytes) store_id(a, dst, particle_id<0>(a, g, s, base + (int64_t)j, 0u));
           } else {
             set_flag(a.flags, FLAG_COUNT);
           }
@@ -1943,15 +1738,7 @@ void launch_deposit(Sim& s, hipStream_t st) {
   a.inv_mean = (double)s.nm * (double)s.nm * (double)s.nm / ((double)s.n * ldexp(1.0, 3 * (8 * s.nchi - 1)));
   a.interleave = s.deposit_variant & 1;
   const dim3 grid((unsigned)cols, (unsigned)nchunk);
-  if (s.deposit_variant & 4) {
-    if (s.deposit_variant & 2) {
-      if (s.nchi == 1) k_deposit_q<1, 512><<<grid, 512, 0, st>>>(a);
-      else k_deposit_q<2, 512><<<grid, 512, 0, st>>>(a);
-    } else {
-      if (s.nchi == 1) k_deposit_q<1, 256><<<grid, 256, 0, st>>>(a);
-      else k_deposit_q<2, 256><<<grid, 256, 0, st>>>(a);
-    }
-  } else if (s.deposit_variant & 2) {
+  if (s.deposit_variant & 2) {
     if (s.nchi == 1) k_deposit<1, 512><<<grid, 512, 0, st>>>(a);
     else k_deposit<2, 512><<<grid, 512, 0, st>>>(a);
   } else {

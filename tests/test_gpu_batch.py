@@ -91,7 +91,6 @@ VARIANTS = [dict(move_variant=0, fft_col_width=8), dict(move_variant=1, fft_col_
             dict(move_variant=2), dict(move_variant=3), dict(move_variant=-1),
             dict(move_variant=0, fft_col_width=16, fft_z_order=1), dict(move_variant=1, fft_col_width=16),
             dict(deposit_variant=1), dict(deposit_variant=2), dict(deposit_variant=3, fft_z_order=1),
-            dict(deposit_variant=4), dict(deposit_variant=6),
             dict(fft_z_layout=1), dict(fft_z_layout=1, fft_col_width=16),
             dict(fft_z_layout=1, fft_col_width=16, fft_z_width=8)]
 
@@ -106,7 +105,7 @@ def test_variants_are_bit_identical(lib, variant):
 def test_variant_validation(lib):
     with lib.Sim(**synth.WORKLOADS["c1_pm32"]) as s:
         before = s.variant
-        for bad in (dict(move_variant=4), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=8),
+        for bad in (dict(move_variant=4), dict(fft_col_width=4), dict(fft_z_order=3), dict(deposit_variant=4),
                     dict(fft_z_layout=2), dict(fft_col_width=8, fft_z_width=16)):
             with pytest.raises(lib.CubeError):
                 s.set_variant(**bad)

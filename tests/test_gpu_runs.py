@@ -254,13 +254,18 @@ def _full_run_power(Sim, name, nbins=None):
 
 
 @pytest.mark.parametrize("name", ["c1_pm32", "c2_pm128", "c3_sibling256"])
-def test_full_run_power_within_one_percent(Sim, name):
-    """P(k) at a = 1 from identical ICs, GPU (compressed, FP32) vs oracle (uncompressed, FP64),
-    k_Nyquist = pi N_m / L. 2-byte positions and velocities: within 1% for every shell below
-    k_Nyquist/2. A 1-byte position or velocity code: within 1% below 0.2 k_Nyquist, the range of the
-    paper's claim, and within 1.5% below k_Nyquist/2 (measured: C1 x1v1 1.2%, from position bins of
-    1/64 fine cell that swallow the slowest early drifts; C2 x2v1 1.06%, from the 255-code velocity
-    quantisation)."""
+def test_full_run_power_against_oracle(Sim, name):
+    """P(k) at a = 1 from identical ICs, GPU (compressed, FP32) vs the oracle (uncompressed, FP64),
+    k_Nyquist = pi N_m / L.
+
+    * Every codec: within 1% of the oracle for k < 0.2 k_Nyquist, the range of the paper's claim
+      (Sec. 3); 2-byte positions and velocities: within 1% for every shell below k_Nyquist/2.
+    * Below k_Nyquist/2 a 1-byte code misses the 1% target: measured C1 x1v1 1.2%, C2 x2v1 1.06%,
+      the C3 sibling x1v1 1.39%. The miss is the compression's: the same run through the FP32
+      step reference of the compressed step (no GPU kernel; tests/golden/*_codec_pk.json, and
+      tests/test_oracle_codec_ablation.py for all four codecs of C1) deviates by as much
+      (C1 1.21%, C2 1.04%), and the GPU run stays within 0.3% of that reference at every shell
+      below k_Nyquist/2. The C3 sibling (no stored reference run) is held to 1.5%."""
     path = os.path.join(HERE, "golden", f"{name}_pk.json")
     if not os.path.exists(path):
         pytest.skip(f"golden file {path} missing (tests/golden/make_golden.py)")
@@ -273,10 +278,19 @@ def test_full_run_power_within_one_percent(Sim, name):
     dev = np.abs(pk / pref - 1)
     half, fifth = dev[k < kny / 2].max(), dev[k < 0.2 * kny].max()
     print(name, f"max |P_gpu/P_oracle - 1|: k<k_Ny/2 {half:.4f}, k<0.2k_Ny {fifth:.4f}")
+    assert fifth < 0.01
     if cfg["x_bytes"] == 2 and cfg["v_bytes"] == 2:
         assert half < 0.01
+        return
+    codec = os.path.join(HERE, "golden", f"{name}_codec_pk.json")
+    if os.path.exists(codec):
+        pc = np.array(json.load(open(codec))["pk"])
+        dc = np.abs(pc / pref - 1)[k < kny / 2].max()
+        gap = np.abs(pk / pc - 1)[k < kny / 2].max()
+        print(name, f"FP32 reference run with the same codes: k<k_Ny/2 {dc:.4f}; GPU vs it {gap:.4f}")
+        assert gap < 0.003
     else:
-        assert fifth < 0.01 and half < 0.015
+        assert half < 0.015
 
 
 def test_determinism(Sim):
