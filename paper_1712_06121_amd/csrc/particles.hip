@@ -1097,6 +1097,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     }
   }
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
+  // scatter: [0] the number of the tile's chunks ranked so far, [1] set if a wait gave up
+  __shared__ uint32_t turn[2];
+  if (threadIdx.x == 0) turn[0] = turn[1] = 0u;
   const float* tdec = NNU == 1 ? tdec_lds : a.tdec;
   const float* edges = NNU == 1 ? edges_lds : a.tedge;
   using BT = std::conditional_t<NNU == 1, int8_t, int16_t>;
@@ -1179,10 +1182,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       for (int d = 0; d < 3; ++d) v[d] = 0.0f;
     }
   };
-  if constexpr (!SCATTER) {
-    // Count pass: the wavefronts take every NW-th chunk of 64 of the tile's particles (its 64 cells in
-    // storage order, one after the other), so that a crowded cell is shared by all of them; the lanes
-    // of a chunk find their cells from the prefix counts by a forward walk shared by the wavefront.
+  // Both passes: the wavefronts take every NW-th chunk of 64 of the tile's particles (its 64 cells
+  // in storage order, one after the other), so that a crowded cell is shared by all of them; the
+  // lanes of a chunk find their cells from the prefix counts by a forward walk shared by the
+  // wavefront.
+  {
     constexpr int NW = NTH / 64;
     const uint32_t tot = pre[TC];
     const CT* chx = static_cast<const CT*>(a.chi);
@@ -1219,9 +1223,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       const uint32_t i = c0 + (uint32_t)lane;
       const bool active = i < tot;
       const int s = sn;
+      const int64_t pc = pn;
       const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
-      // the codes of the next chunk are requested before this chunk's atomics are issued (past the
-      // end the request repeats a particle of this chunk)
+      // the codes of the next chunk are requested before this chunk's atomics and stores are issued
+      // (past the end the request repeats a particle of this chunk)
       if (c0 + 64u * NW < tot) locate(c0 + 64u * NW, sn, pn);
       load_at(pn);
       const int ci = s % T, o1 = (s / T) % T, o2 = s / (T * T);
@@ -1229,148 +1234,117 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       int k[3], cq[3];
       physics(active, s, ci, o1, o2, chc, nuc, v, k, cq);
       const int dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1);
-      const uint32_t cbeg = pre[s], cend = pre[s + 1];
-      const uint32_t j0 = c0, j = i;
-      long long q[4];
-      velocity_moments(v, q);  // inactive lanes hold v = 0
-      const bool stay = active && dcode == 13;
-      const unsigned long long smask = __ballot(stay);
-      // stayers: one prefix sum over the chunk, then the difference over each cell's lanes
-      unsigned long long ps[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) ps[d] = wave_scan_u64(stay ? (unsigned long long)q[d] : 0ull);
-      // The last lane of each of the chunk's cells adds the cell's stayers: their number
-      // and moment sums are the differences of the inclusive scans at that lane and at the lane
-      // before the cell's first one in the chunk (fetched with one lane shuffle per word).
-      const int la = cbeg > j0 ? (int)(cbeg - j0) : 0;  // the cell's first lane in the chunk
-      const int from = (la > 0 ? la - 1 : 0) * 4;
-      const bool tail = active && (j + 1u == cend || lane == 63);
-      const unsigned long long seg = (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)) & ~((1ull << la) - 1ull);
-      const uint32_t nst = (uint32_t)__popcll(smask & seg);
-      unsigned long long sum4[4];
-#pragma unroll
-      for (int d = 0; d < 4; ++d) {
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)ps[d]);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(ps[d] >> 32));
-        sum4[d] = ps[d] - (la > 0 ? (((unsigned long long)hi << 32) | lo) : 0ull);
-      }
-      if (tail && nst > 0u) {
-        atomicAdd(&grp[s * 27 + 13], nst);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) atomicAdd(&omom[s * 4 + d], sum4[d]);
-      }
-      if (active && !stay) {
-        atomicAdd(&grp[s * 27 + dcode], 1u);
-        // new cell inside the tile: the tile's LDS accumulators; in the ring: the global ones
-        const int tx = ci + k[0], ty = o1 + k[1], tz = o2 + k[2];
-        if (tx >= 0 && tx < T && ty >= 0 && ty < T && tz >= 0 && tz < T) {
-          const int so = tx + T * (ty + T * tz);
-#pragma unroll
-          for (int d = 0; d < 4; ++d) atomicAdd(&omom[so * 4 + d], (unsigned long long)q[d]);
-        } else {
-          // the cell index and byte offsets fit 32 bits (nc^3 < 2^28); the plane bases are uniform
-          const uint32_t nx = (uint32_t)wrapi(g.cx0 + tx, a.nc), ny = (uint32_t)wrapi(g.cy0 + ty, a.nc);
-          const uint32_t nz = (uint32_t)wrapi(g.cz0 + tz, a.nc), ncu = (uint32_t)a.nc;
-          const uint32_t boff = (nx + ncu * (ny + ncu * nz)) * 8u;
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            char* plane = reinterpret_cast<char*>(a.mom + (int64_t)d * a.nc3);
-            atomicAdd(reinterpret_cast<unsigned long long*>(plane + boff), (unsigned long long)q[d]);
-          }
-        }
-      }
-    }
-  } else {
-    // Scatter pass: each wave takes one row of T cells along x (16 rows, 16 waves); the row's
-    // particles are contiguous, so its 64-lane chunks stay full across the row's cell boundaries,
-    // and only this wave ranks particles of the row's cells.
-    for (int row = wave; row < T * T; row += NTH / 64) {
-      const int s0 = row * T, o1 = row % T, o2 = row / T;
-      const uint32_t r0 = pre[s0];
-      const uint32_t p1 = pre[s0 + 1] - r0, p2 = pre[s0 + 2] - r0, p3 = pre[s0 + 3] - r0, nrow = pre[s0 + T] - r0;
-      const int64_t base = (int64_t)start[s0];
-      const CT* chx = static_cast<const CT*>(a.chi) + base;
-      const NT* nux = static_cast<const NT*>(a.nu) + base;
-      // the next chunk's codes are requested before this chunk's stores are issued, so that waiting
-      // for them never waits for those (the vector memory counter is in order); past the row's end
-      // the request repeats its last particle, so it needs no branch
-      int chn[3] = {0, 0, 0}, nun[3] = {0, 0, 0};
-      auto load_chunk = [&](uint32_t jj) {
-        jj = min(jj, nrow - 1);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          chn[d] = (int)chx[d * a.cap + jj];
-          nun[d] = (int)nux[d * a.cap + jj];
-        }
-      };
-      if (nrow > 0) load_chunk(lane);
-      uint32_t scnt[T] = {0u, 0u, 0u, 0u};  // stayers ranked so far per cell of the row
-      for (uint32_t j0 = 0; j0 < nrow; j0 += 64) {
-        const uint32_t j = j0 + lane;
-        const bool active = j < nrow;
-        const int ci = (int)(j >= p1) + (int)(j >= p2) + (int)(j >= p3);  // cell of the row
-        const int s = s0 + ci;
-        const int chc[3] = {chn[0], chn[1], chn[2]}, nuc[3] = {nun[0], nun[1], nun[2]};
-        load_chunk(j + 64);
-        float v[3];
-        int k[3], cq[3];
-        physics(active, s, ci, o1, o2, chc, nuc, v, k, cq);
-        const int dcode = (k[2] + 1) * 9 + (k[1] + 1) * 3 + (k[0] + 1);
-        // rank among the lanes with the same (cell of the row, displacement), in storage order.
-        // Stayers: a running count per cell of the row, kept by the wave. Movers (few): one pass
-        // per distinct key, counters in LDS.
-        uint32_t rin = 0, gbase = 0;
+      if constexpr (!SCATTER) {
+        const uint32_t cbeg = pre[s], cend = pre[s + 1];
+        long long q[4];
+        velocity_moments(v, q);  // inactive lanes hold v = 0
         const bool stay = active && dcode == 13;
         const unsigned long long smask = __ballot(stay);
-        const int cfirst = __builtin_amdgcn_readfirstlane(ci);
-        const uint32_t jend = nrow - j0 < 64u ? nrow - j0 : 64u;  // active lanes
-        const int clast = __builtin_amdgcn_readlane(ci, (int)jend - 1);
-        const uint32_t bnd[5] = {0u, p1, p2, p3, nrow};
+        // stayers: one prefix sum over the chunk, then the difference over each cell's lanes
+        unsigned long long ps[4];
 #pragma unroll
-        for (int cc = 0; cc < T; ++cc) {
-          if (cc < cfirst || cc > clast) continue;
-          // lanes [la, le) (wave-uniform)
-          const uint32_t la = (uint32_t)__builtin_amdgcn_readfirstlane((int)(bnd[cc] > j0 ? bnd[cc] - j0 : 0u));
-          const uint32_t le =
-              (uint32_t)__builtin_amdgcn_readfirstlane((int)(bnd[cc + 1] - j0 < jend ? bnd[cc + 1] - j0 : jend));
-          if (la >= le) continue;
-          const unsigned long long seg = (le == 64u ? ~0ull : ((1ull << le) - 1ull)) & ~((1ull << la) - 1ull);
-          const unsigned long long m = smask & seg;
-          if (stay && ci == cc) {
-            rin = lanes_below(m);
-            gbase = scnt[cc];
-          }
-          scnt[cc] += (uint32_t)__popcll(m);
+        for (int d = 0; d < 4; ++d) ps[d] = wave_scan_u64(stay ? (unsigned long long)q[d] : 0ull);
+        // The last lane of each of the chunk's cells adds the cell's stayers: their number
+        // and moment sums are the differences of the inclusive scans at that lane and at the lane
+        // before the cell's first one in the chunk (fetched with one lane shuffle per word).
+        const int la = cbeg > c0 ? (int)(cbeg - c0) : 0;  // the cell's first lane in the chunk
+        const int from = (la > 0 ? la - 1 : 0) * 4;
+        const bool tail = active && (i + 1u == cend || lane == 63);
+        const unsigned long long seg = (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)) & ~((1ull << la) - 1ull);
+        const uint32_t nst = (uint32_t)__popcll(smask & seg);
+        unsigned long long sum4[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)ps[d]);
+          const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(from, (int)(uint32_t)(ps[d] >> 32));
+          sum4[d] = ps[d] - (la > 0 ? (((unsigned long long)hi << 32) | lo) : 0ull);
         }
-        const int key = (ci << 5) | dcode;
-        unsigned long long todo = __ballot(active && !stay);
-        while (todo) {
-          const int leader = (int)__builtin_ctzll(todo);
-          const int lk = __builtin_amdgcn_readlane(key, leader);
-          const unsigned long long m = __ballot(active && key == lk);
-          const int gi = (s0 + (lk >> 5)) * 27 + (lk & 31);
-          const uint32_t b0 = grp[gi];
-          if (active && key == lk) {
-            rin = lanes_below(m);
-            gbase = b0;
-          }
-          if (lane == leader) grp[gi] = b0 + (uint32_t)__popcll(m);
-          todo &= ~m;
+        if (tail && nst > 0u) {
+          atomicAdd(&grp[s * 27 + 13], nst);
+#pragma unroll
+          for (int d = 0; d < 4; ++d) atomicAdd(&omom[s * 4 + d], sum4[d]);
         }
+        if (active && !stay) {
+          atomicAdd(&grp[s * 27 + dcode], 1u);
+          // new cell inside the tile: the tile's LDS accumulators; in the ring: the global ones
+          const int tx = ci + k[0], ty = o1 + k[1], tz = o2 + k[2];
+          if (tx >= 0 && tx < T && ty >= 0 && ty < T && tz >= 0 && tz < T) {
+            const int so = tx + T * (ty + T * tz);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) atomicAdd(&omom[so * 4 + d], (unsigned long long)q[d]);
+          } else {
+            // the cell index and byte offsets fit 32 bits (nc^3 < 2^28); the plane bases are uniform
+            const uint32_t nx = (uint32_t)wrapi(g.cx0 + tx, a.nc), ny = (uint32_t)wrapi(g.cy0 + ty, a.nc);
+            const uint32_t nz = (uint32_t)wrapi(g.cz0 + tz, a.nc), ncu = (uint32_t)a.nc;
+            const uint32_t boff = (nx + ncu * (ny + ncu * nz)) * 8u;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+              char* plane = reinterpret_cast<char*>(a.mom + (int64_t)d * a.nc3);
+              atomicAdd(reinterpret_cast<unsigned long long*>(plane + boff), (unsigned long long)q[d]);
+            }
+          }
+        }
+      } else {
+        // Scatter: the rank inside the (new cell, source offset) slot is the number of the
+        // particles before this one in storage order with the same (source cell, displacement).
+        // Within the chunk it comes from the lanes with the same key (one ballot per key bit);
+        // across chunks from the running count per key in LDS, which the chunks update strictly in
+        // storage order: chunk c waits until c chunks have been ranked (wavefronts of one
+        // workgroup are all resident, and chunk c - 1's wavefront never waits for chunk c, so the
+        // wait ends; it is also bounded, and one that gives up raises an error flag).
+        const int key = s * 27 + dcode;  // < 64 * 27, 11 bits
+        unsigned long long peers = __ballot(active);
+#pragma unroll
+        for (int bt = 0; bt < 11; ++bt) {
+          const bool bit = (key >> bt) & 1;
+          const unsigned long long bb = __ballot(active && bit);
+          peers &= bit ? bb : ~bb;
+        }
+        const uint32_t rin = lanes_below(peers), npeer = (uint32_t)__popcll(peers);
+        // the ranks are formed before the turn is awaited (the compiler would otherwise move them
+        // into the ordered section, which the chunks pass through one at a time)
+        asm volatile("" ::"v"(rin), "v"(npeer));
+        // destination cell data, requested before the turn is awaited
+        const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
+        const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
+        const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
+        uint64_t dbase = 0;
+        float inv = 0.0f, vcn[3] = {0.0f, 0.0f, 0.0f};
         if (active) {
-          const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
-          const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
-          const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
-          const uint64_t dst = a.off_n[cn] + a.slot[(int64_t)(26 - dcode) * a.nc3 + cn] + gbase + (uint32_t)rin;
+          dbase = a.off_n[cn] + a.slot[(int64_t)(26 - dcode) * a.nc3 + cn];
+          inv = a.vinv[cn];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) vcn[d] = a.vc_n[d * a.nc3 + cn];
+        }
+        const uint32_t chunk = c0 / 64u;
+        {
+          uint32_t spins = 0;
+          while (__hip_atomic_load(&turn[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != chunk &&
+                 __hip_atomic_load(&turn[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins == (1u << 22)) {
+              if (lane == 0) {
+                __hip_atomic_store(&turn[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                set_flag(a.flags, FLAG_COUNT);
+              }
+              break;
+            }
+          }
+        }
+        uint32_t b0 = 0u;
+        if (active) b0 = grp[key];
+        if (active && rin == 0u) grp[key] = b0 + npeer;
+        if (lane == 0) __hip_atomic_store(&turn[0], chunk + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (active) {
+          const uint64_t dst = dbase + b0 + rin;
           if (dst < (uint64_t)a.cap) {
-            const float inv = a.vinv[cn];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-              const float u = (v[d] - a.vc_n[d * a.nc3 + cn]) * inv;
+              const float u = (v[d] - vcn[d]) * inv;
               nu_n[d * a.cap + dst] = (NT)encode_nu<false>(u, edges, bucket, a.nbucket, a.vhalf);
               chi_n[d * a.cap + dst] = (CT)cq[d];
             }
-            if (a.pid_bytes) store_id(a, dst, particle_id<0>(a, g, s, base + (int64_t)j, 0u));
+            if (a.pid_bytes) store_id(a, dst, particle_id<0>(a, g, s, pc, 0u));
           } else {
             set_flag(a.flags, FLAG_COUNT);
           }

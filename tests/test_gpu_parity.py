@@ -191,6 +191,28 @@ def test_move_bit_exact(Sim, nchi, nnu, mode, nm, n, vscale):
     assert_state_equal(got2, exp2, "second move")
 
 
+@pytest.mark.parametrize("move_variant", [1, 0])
+def test_move_crowded_cell_bit_exact(Sim, move_variant):
+    """One coarse cell holding most of the particles (about 1400 chunks of 64, taken by all the
+    wavefronts of its tile in turn): the ranks inside the new cells still follow storage order."""
+    nm, n = 32, 100000
+    x, v = synth.particle_cloud(17, n, nm, vscale=0.5, clump_frac=0.9, n_clumps=1, clump_radius=0.7)
+    st = twin.load(x, v, nm // 4, 1, 1, 1)
+    assert st.cnt.max() > 40000
+    phi = synth.smooth_potential(9, nm, amp=0.5)
+    kf, df = np.float32(-1.3 / 12.0), np.float32(0.5)
+    exp, info = twin.move(st, phi, kf, df, sigma_mode=1, return_info=True)
+    assert not info["cfl"]
+    assert (info["dcode"] != 13).mean() > 0.05
+    with Sim(np_for(nm), nm, 100.0, sigma_mode=1, capacity=n) as sim:
+        sim.set_state(st.cnt, st.chi, st.nu, st.vc, st.vs)
+        sim.set_variant(move_variant=move_variant)
+        sim.set_mesh(phi)
+        sim.stage_move(kf, df)
+        got = sim.get_state()
+    assert_state_equal(got, exp, f"crowded cell, move variant {move_variant}")
+
+
 def test_cfl_violation_reported(Sim):
     from paper_1712_06121_amd import CubeError
     nm, nc, n = 64, 16, 5000
