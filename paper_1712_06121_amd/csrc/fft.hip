@@ -38,9 +38,23 @@ __device__ __forceinline__ float2 mul_pi2(float2 a) {
   return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
 
-template <int DIR>
+// twiddle exp(DIR 2 pi i idx / n) from a table of exp(-2 pi i t / n): the whole table (QN = 0) or,
+// for QN = n, its first quarter t = 0 .. n/4 - 1, the rest following by exact quarter turns
+// (exp(-2 pi i (q n/4 + u) / n) = (-i)^q exp(-2 pi i u / n))
+template <int DIR, int QN = 0>
 __device__ __forceinline__ float2 twid(const float2* __restrict__ tw, int idx) {
-  float2 w = tw[idx];
+  float2 w;
+  if constexpr (QN == 0) {
+    w = tw[idx];
+  } else {
+    constexpr int Q = QN / 4;
+    const int q = idx / Q, u = idx - q * Q;
+    const float2 b = tw[u];
+    // odd q swaps the components; the signs flip as (q & 2) for x and ((q + 1) & 2) for y
+    const float sx = (q & 1) ? b.y : b.x, sy = (q & 1) ? b.x : b.y;
+    w = make_float2(__uint_as_float(__float_as_uint(sx) ^ ((uint32_t)(q & 2) << 30)),
+                    __uint_as_float(__float_as_uint(sy) ^ ((uint32_t)((q + 1) & 2) << 30)));
+  }
   if (DIR > 0) w.y = -w.y;
   return w;
 }
@@ -117,8 +131,9 @@ template <>
 __device__ __forceinline__ void dft<8, 1>(float2* v) { dft8<1>(v); }
 
 // One radix-R Stockham stage over NL lines of length L held in LDS. Element t of line l sits at
-// lds[l * LS + t * TS]. Twiddles come from a table of exp(-2 pi i t / (L * TWS)).
-template <int L, int R, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS>
+// lds[l * LS + t * TS]. Twiddles come from a table of exp(-2 pi i t / (L * TWS)), or with QT from
+// the first quarter of it.
+template <int L, int R, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS, bool QT = false>
 __device__ __forceinline__ void stockham_stage(float2* lds, const float2* __restrict__ tw) {
   constexpr int NBF = L / R;
   constexpr int NB = NL * NBF;
@@ -136,7 +151,7 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* __rest
       if (NS > 1) {
         const int k = j % NS;
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], twid<DIR>(tw, r * k * (L / (NS * R)) * TWS));
+        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], twid<DIR, QT ? L * TWS : 0>(tw, r * k * (L / (NS * R)) * TWS));
       }
       dft<R, DIR>(v[p]);
     }
@@ -158,12 +173,12 @@ __device__ __forceinline__ void stockham_stage(float2* lds, const float2* __rest
   __syncthreads();
 }
 
-template <int L, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS>
+template <int L, int NS, int NL, int LS, int TS, int BLOCK, int DIR, int TWS, bool QT = false>
 __device__ __forceinline__ void fft_lds(float2* lds, const float2* __restrict__ tw) {
   if constexpr (NS < L) {
     constexpr int R = next_radix(L / NS);
-    stockham_stage<L, R, NS, NL, LS, TS, BLOCK, DIR, TWS>(lds, tw);
-    fft_lds<L, NS * R, NL, LS, TS, BLOCK, DIR, TWS>(lds, tw);
+    stockham_stage<L, R, NS, NL, LS, TS, BLOCK, DIR, TWS, QT>(lds, tw);
+    fft_lds<L, NS * R, NL, LS, TS, BLOCK, DIR, TWS, QT>(lds, tw);
   }
 }
 
@@ -188,6 +203,10 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
                                                   const float2* __restrict__ tw) {
   constexpr int H = RowCfg<N>::H, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
   __shared__ float2 lds[NL * H];
+  // the first quarter of the twiddle table in LDS: the stages then make no global read, whose
+  // latency every stage would otherwise wait for
+  __shared__ float2 twq[N / 4];
+  for (int i = threadIdx.x; i < N / 4; i += BLOCK) twq[i] = tw[i];
   const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NL;
   constexpr int F4 = N / 4;
   constexpr int LPT = (NL * F4 + BLOCK - 1) / BLOCK;
@@ -209,7 +228,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
     }
   }
   __syncthreads();
-  fft_lds<H, 1, NL, H, 1, BLOCK, -1, 2>(lds, tw);
+  fft_lds<H, 1, NL, H, 1, BLOCK, -1, 2, true>(lds, twq);
   constexpr int NP = H / 2 + 1;
   for (int i = threadIdx.x; i < NL * NP; i += BLOCK) {
     const int l = i / NP, k = i % NP;
@@ -231,6 +250,8 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
   constexpr int H = N / 2, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
   constexpr int LS = H + 1;
   __shared__ float2 lds[NL * LS];
+  __shared__ float2 twq[N / 4];  // the first quarter of the twiddle table
+  for (int i = threadIdx.x; i < N / 4; i += BLOCK) twq[i] = tw[i];
   const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NL;
   constexpr int LPT = (NL * LS + BLOCK - 1) / BLOCK;
   float2 stage[LPT];
@@ -259,7 +280,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
     if (k != 0 && k != H - k) lds[l * LS + H - k] = make_float2(a.x + b.y, -a.y + b.x);
   }
   __syncthreads();
-  fft_lds<H, 1, NL, LS, 1, BLOCK, 1, 2>(lds, tw);
+  fft_lds<H, 1, NL, LS, 1, BLOCK, 1, 2, true>(lds, twq);
   constexpr int F4 = N / 4;
   for (int i = threadIdx.x; i < NL * F4; i += BLOCK) {
     const int l = i / F4, c = i % F4;
@@ -308,6 +329,13 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
                                                                  const float2* __restrict__ tw, ColArgs a) {
   constexpr int BLOCK = ColCfg<N, BX>::BLOCK;
   __shared__ float2 lds[N * BX];
+  // the first quarter of the twiddle table and (z pass) the squared wavenumbers, in LDS: the
+  // transforms then make no global read, whose latency every stage would otherwise wait for
+  __shared__ float2 twq[N / 4];
+  __shared__ float k2s[MODE == COL_GREEN ? N : 1];
+  for (int i = threadIdx.x; i < N / 4; i += BLOCK) twq[i] = tw[i];
+  if constexpr (MODE == COL_GREEN)
+    for (int i = threadIdx.x; i < N; i += BLOCK) k2s[i] = a.k2[i];
   const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
   const unsigned lb = a.order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
   int cb, o;
@@ -348,15 +376,15 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
   }
   __syncthreads();
   if constexpr (MODE == COL_FWD || MODE == COL_GREEN || MODE == COL_POWER)
-    fft_lds<N, 1, BX, 1, BX, BLOCK, -1, 1>(lds, tw);
+    fft_lds<N, 1, BX, 1, BX, BLOCK, -1, 1, true>(lds, twq);
   if constexpr (MODE == COL_GREEN) {
     // z pass: t = z frequency index, column x_c = cb*BX + b, o = y index
-    const float ky2 = a.k2[o];
+    const float ky2 = k2s[o];
     if (!a.ct.spec) {
       for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
         const int t = i / BX, b = i % BX;
         const int xc = cb * BX + b;
-        const float kk = a.k2[xc] + ky2 + a.k2[t];
+        const float kk = k2s[xc] + ky2 + k2s[t];
         const float g = (xc == 0 && o == 0 && t == 0) ? 0.0f : a.gconst / kk;
         const float2 v = lds[i];
         lds[i] = make_float2(v.x * g, v.y * g);
@@ -372,7 +400,7 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
       for (int i = threadIdx.x; i < N * BX; i += BLOCK) {
         const int t = i / BX, b = i % BX;
         const int xc = cb * BX + b;
-        const float kk = a.k2[xc] + ky2 + a.k2[t];
+        const float kk = k2s[xc] + ky2 + k2s[t];
         const float g = (xc == 0 && o == 0 && t == 0) ? 0.0f : a.gconst / kk;
         const float s = expf(-kk * c.rs2);
         const float2 v = lds[i];
@@ -439,7 +467,7 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
     return;
   }
   if constexpr (MODE == COL_INV || MODE == COL_GREEN || MODE == COL_PSI)
-    fft_lds<N, 1, BX, 1, BX, BLOCK, 1, 1>(lds, tw);
+    fft_lds<N, 1, BX, 1, BX, BLOCK, 1, 1, true>(lds, twq);
   const int64_t obase = (int64_t)o * gt.o_s + (int64_t)(cb / gt.cb_r) * gt.cb_s + (int64_t)(cb % gt.cb_r) * BX;
   for (int i = threadIdx.x; i < N * Q; i += BLOCK) {
     const int t = i / Q, c = i % Q;
@@ -798,9 +826,19 @@ void fft_plan_create(Sim& s, FFTPlan& pl, int n) {
   std::vector<float2> tw(n);
   std::vector<float> k2(n);
   const double two_pi = 6.283185307179586476925286766559;
-  for (int t = 0; t < n; ++t) {
+  // the first quarter from the cosine and sine, the rest by exact quarter turns of it, as the
+  // transforms, which keep only the first quarter in LDS, form them
+  const int q = n / 4;
+  for (int t = 0; t < q; ++t) {
     const double ang = -two_pi * (double)t / (double)n;
     tw[t] = make_float2((float)cos(ang), (float)sin(ang));
+  }
+  for (int t = q; t < n; ++t) {
+    const float2 b = tw[t % q];
+    const int r = t / q;
+    tw[t] = r == 1 ? make_float2(b.y, -b.x) : (r == 2 ? make_float2(-b.x, -b.y) : make_float2(-b.y, b.x));
+  }
+  for (int t = 0; t < n; ++t) {
     const int f = t <= n / 2 ? t : t - n;
     const double k = two_pi * (double)f / (double)n;
     k2[t] = (float)(k * k);
