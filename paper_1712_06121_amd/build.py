@@ -29,6 +29,7 @@ PER_FILE = {
     "batch.cpp": ["-ffp-contract=off"],
     "serve.cpp": ["-ffp-contract=off"],
     "noalloc.hip": ["-ffp-contract=off"],
+    "sort.hip": [],
 }
 
 

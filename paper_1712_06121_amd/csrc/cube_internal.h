@@ -234,6 +234,12 @@ void launch_load(Sim& s, const double* dx, const float* dv, int64_t n, hipStream
 // 1-byte counts into rho1 (nc3 bytes, device) and the counts >= 255 in cell order into over
 // (nc3 entries at most, device); returns the number of the latter
 int64_t launch_counts_u8(Sim& s, uint8_t* rho1, uint32_t* over, hipStream_t st);
+// stable sort of n (key, value) pairs by key (keys <= max_key), ping-ponging between the given
+// buffer pairs; *key_sorted / *val_sorted receive the pair that holds the result (sort.hip)
+void sort_pairs_by_key(Sim& s, uint32_t* key, uint32_t* val, uint32_t* key_alt, uint32_t* val_alt, int64_t n,
+                       uint32_t max_key, hipStream_t st, uint32_t** key_sorted, uint32_t** val_sorted);
+// the values >= 255 of cnt[0 .. n) in order into out; returns their number (sort.hip)
+int64_t select_at_least_255(Sim& s, const uint32_t* cnt, int64_t n, uint32_t* out, hipStream_t st);
 // largest |v|^2 of the current state (uses amax as scratch; synchronises)
 float launch_state_speed2(Sim& s, hipStream_t st);
 // particle IDs 0 .. n-1 in storage order (when IDs are enabled)

@@ -20,7 +20,6 @@
 #include <cstring>
 #include <type_traits>
 
-#include <rocprim/rocprim.hpp>
 
 #include "cube_internal.h"
 
@@ -1900,15 +1899,12 @@ void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, h
     k_load_codes<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(a);
     CUBE_HIP(hipGetLastError());
   }
-  // stable radix sort of (cell id, input index)
-  size_t tmp_bytes = 0;
-  const unsigned end_bit = 32;
-  CUBE_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, key, key2, idx, idx2, (size_t)n, 0, end_bit, st));
-  void* tmp = s.dmalloc(tmp_bytes > 0 ? tmp_bytes : 16);
-  CUBE_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, key, key2, idx, idx2, (size_t)n, 0, end_bit, st));
+  // stable sort of (cell id, input index) by cell id
+  uint32_t *ks = key, *is = idx;
+  sort_pairs_by_key(s, key, idx, key2, idx2, n, (uint32_t)(s.nc3 - 1), st, &ks, &is);
   link_scan_finalize(s, nxt, s.cnt[nxt], st);
 #define CUBE_ENC(X, V)                                                                                       \
-  k_load_encode<X, V><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(key2, idx2, chi_tmp, v_tmp, n, s.chi[nxt], \
+  k_load_encode<X, V><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(ks, is, chi_tmp, v_tmp, n, s.chi[nxt],    \
                                                                    s.nu[nxt], s.capacity, s.vc[nxt], s.vinv, \
                                                                    s.nc3, s.tedge, s.tbucket, s.nbucket, (s.vm - 1) / 2, \
                                                                    s.pid[nxt], s.pid_bytes)
@@ -1918,7 +1914,6 @@ void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, h
   }
 #undef CUBE_ENC
   CUBE_HIP(hipStreamSynchronize(st));
-  s.dfree(tmp);
   s.dfree(v_tmp);
   s.dfree(chi_tmp);
   s.dfree(key);
@@ -1990,26 +1985,12 @@ __global__ void k_counts_u8(const uint32_t* cnt, int64_t nc3, uint8_t* rho1) {
   rho1[c] = (uint8_t)(v < 255u ? v : 255u);
 }
 
-struct AtLeast255 {
-  __device__ bool operator()(uint32_t v) const { return v >= 255u; }
-};
-
 int64_t launch_counts_u8(Sim& s, uint8_t* rho1, uint32_t* over, hipStream_t st) {
   const uint32_t* cnt = s.cnt[s.cur];
   k_counts_u8<<<(unsigned)((s.nc3 + 255) / 256), 256, 0, st>>>(cnt, s.nc3, rho1);
   CUBE_HIP(hipGetLastError());
   // the true counts of the cells marked 255, in cell order (a stable selection)
-  size_t* nsel = static_cast<size_t*>(s.dmalloc(sizeof(size_t)));
-  size_t tmp_bytes = 0;
-  CUBE_HIP(rocprim::select(nullptr, tmp_bytes, cnt, over, nsel, (size_t)s.nc3, AtLeast255(), st));
-  void* tmp = s.dmalloc(tmp_bytes > 0 ? tmp_bytes : 16);
-  CUBE_HIP(rocprim::select(tmp, tmp_bytes, cnt, over, nsel, (size_t)s.nc3, AtLeast255(), st));
-  size_t n = 0;
-  CUBE_HIP(hipMemcpyAsync(&n, nsel, sizeof(size_t), hipMemcpyDeviceToHost, st));
-  CUBE_HIP(hipStreamSynchronize(st));
-  s.dfree(tmp);
-  s.dfree(nsel);
-  return (int64_t)n;
+  return select_at_least_255(s, cnt, s.nc3, over, st);
 }
 
 void launch_noise(const FFTPlan& pl, float* out, uint64_t seed, hipStream_t st) {

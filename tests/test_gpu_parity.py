@@ -46,6 +46,18 @@ def test_load_bit_exact(Sim, nchi, nnu, mode):
         assert_state_equal(sim.get_state(), ref, f"load x{nchi}v{nnu}")
 
 
+def test_load_many_tiles_bit_exact(Sim):
+    """The load path's stable sort by cell over many tiles of 4096 and three 8-bit digit passes
+    (2^18 coarse cells), with crowded cells whose particles span tiles."""
+    nm, nc, n = 256, 64, 600011
+    x, v = synth.particle_cloud(29, n, nm, clump_frac=0.5, n_clumps=20, clump_radius=2.0)
+    ref = twin.load(x, v, nc, 1, 1, 1)
+    assert ref.cnt.max() > 4096
+    with Sim(np_for(nm), nm, 100.0, capacity=n) as sim:
+        sim.load_particles(x, v)
+        assert_state_equal(sim.get_state(), ref, "load, many tiles")
+
+
 def test_tables_match(Sim):
     for nnu in (1, 2):
         with Sim(32, 64, 100.0, v_bytes=nnu) as sim:

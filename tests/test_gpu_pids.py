@@ -192,6 +192,26 @@ def test_displacement_offsets_against_oracle(lib):
     assert med["x1v1"] < 0.1 * np.median(absd)
 
 
+def test_one_byte_count_export_over_many_tiles(lib):
+    """The ordered selection of the counts of 255 or more over 32^3 cells (eight tiles of 4096),
+    with overflow cells in several tiles."""
+    from oracle import codec
+    cfg = dict(synth.WORKLOADS["c1_pm32"], np_side=32, nm_side=128, nc_side=32, capacity=80000)
+    g = np.random.default_rng(31)
+    x = [g.uniform(0, 128, size=(30000, 3))]
+    for c in range(11):
+        cell = g.integers(0, 32, size=3)
+        x.append(cell * 4.0 + g.uniform(0, 4, size=(255 + 37 * c, 3)))
+    x = np.concatenate(x)
+    with lib.Sim(**cfg) as sim:
+        sim.load_particles(x, np.zeros_like(x))
+        cnt = sim.get_counts()
+        rho1, over = sim.get_counts_u8()
+    r0, o0 = codec.counts_to_u8(cnt)
+    assert len(o0) >= 11
+    assert np.array_equal(rho1, r0) and np.array_equal(over, o0)
+
+
 def test_one_byte_count_export_with_overflow_cells(lib):
     """The checkpoint's 1-byte rho_c (Sec. 2.1) with cells of 255 or more particles."""
     from oracle import codec
