@@ -211,7 +211,9 @@ int cube_get_power_noalloc(cube_sim* sim, int32_t nbins, double* k, double* pk, 
 int cube_get_cross_power(cube_sim* a, cube_sim* b, int32_t nbins, double* k, double* paa, double* pbb,
                          double* pab, double* nmodes);
 
-/* Checkpoint, the paper's "disjoint state" {rho_c, v_c, chi, nu} (Sec. 2.3.1): host buffers.
+/* Checkpoint, the paper's "disjoint state" {rho_c, v_c, chi, nu} (Sec. 2.3.1): host buffers
+ * (cube_get_state also accepts device buffers of the simulation's GPU: the copy direction follows
+ * the pointers).
  * cnt: nc^3 uint32; chi: 3 planes of n codes (uint8 chi+128 for x_bytes 1, uint16 chi+32768
  * for 2); nu: 3 planes of n codes (int8 or int16); vc: 3 planes of nc^3 FP32; vs: nc^3 FP32
  * decode scales sigma sqrt(2/pi) of Eq. (v). cube_get_state writes them (n = current count);
@@ -269,8 +271,9 @@ int cube_stage_solve(cube_sim* sim);
 /* Kick + drift + re-encode + counting sort with the potential held in the mesh:
  * v += kfac * D (D the unnormalised 4-point gradient, so kfac = -K/12), x += dfac * v. */
 int cube_stage_move(cube_sim* sim, float kfac, float dfac);
-/* Copy the real-space mesh (nm^3 FP32, x fastest) to or from host memory. */
-int cube_get_mesh(cube_sim* sim, float* host_dst);
+/* Copy the real-space mesh (nm^3 FP32, x fastest) to or from host memory (cube_get_mesh also
+ * writes device memory of the simulation's GPU: the copy direction follows the pointer). */
+int cube_get_mesh(cube_sim* sim, float* dst);
 int cube_set_mesh(cube_sim* sim, const float* host_src);
 /* Zel'dovich displacement (3 planes of np^3 FP32, fine cells, lattice order) of the last
  * cube_init_ic, computed again from the noise. */

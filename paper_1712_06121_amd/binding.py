@@ -402,12 +402,26 @@ class Sim:
         self._check(self._lib.cube_get_cross_power(self._h, other._h, nb, *(_ptr(x) for x in out)))
         return tuple(out)
 
-    def get_state(self) -> dict:
+    def get_state(self, device: bool = False) -> dict:
+        """The disjoint state as numpy arrays, or with device=True as torch tensors on the
+        simulation's GPU (cnt and the codes as int32 / uint8 / int8 / int16 tensors of the same bits)."""
         n = self.n
         nc3 = self.nc**3
-        st = dict(cnt=np.empty(nc3, np.uint32), chi=np.empty((3, n), self.chi_dtype), nu=np.empty((3, n), self.nu_dtype),
-                  vc=np.empty((3, nc3), np.float32), vs=np.empty(nc3, np.float32))
-        view = CubeStateView(_ptr(st["cnt"]), _ptr(st["chi"]), _ptr(st["nu"]), _ptr(st["vc"]), _ptr(st["vs"]), n, 0.0, 0)
+        if device:
+            import torch
+            tdt = {np.dtype(np.uint8): torch.uint8, np.dtype(np.int8): torch.int8, np.dtype(np.uint16): torch.int16,
+                   np.dtype(np.int16): torch.int16}
+            st = dict(cnt=torch.empty(nc3, dtype=torch.int32, device="cuda"),
+                      chi=torch.empty((3, n), dtype=tdt[np.dtype(self.chi_dtype)], device="cuda"),
+                      nu=torch.empty((3, n), dtype=tdt[np.dtype(self.nu_dtype)], device="cuda"),
+                      vc=torch.empty((3, nc3), dtype=torch.float32, device="cuda"),
+                      vs=torch.empty(nc3, dtype=torch.float32, device="cuda"))
+            ptr = {k: c_void_p(t.data_ptr()) for k, t in st.items()}
+        else:
+            st = dict(cnt=np.empty(nc3, np.uint32), chi=np.empty((3, n), self.chi_dtype),
+                      nu=np.empty((3, n), self.nu_dtype), vc=np.empty((3, nc3), np.float32), vs=np.empty(nc3, np.float32))
+            ptr = {k: _ptr(a) for k, a in st.items()}
+        view = CubeStateView(ptr["cnt"], ptr["chi"], ptr["nu"], ptr["vc"], ptr["vs"], n, 0.0, 0)
         self._check(self._lib.cube_get_state(self._h, byref(view)))
         st["a"] = view.a
         st["steps_done"] = view.steps_done
@@ -448,7 +462,13 @@ class Sim:
     def stage_move(self, kfac: float, dfac: float):
         self._check(self._lib.cube_stage_move(self._h, c_float(kfac), c_float(dfac)))
 
-    def get_mesh(self) -> np.ndarray:
+    def get_mesh(self, device: bool = False):
+        """The real-space mesh [z, y, x]: numpy, or with device=True a torch tensor on the GPU."""
+        if device:
+            import torch
+            out = torch.empty((self.nm,) * 3, dtype=torch.float32, device="cuda")
+            self._check(self._lib.cube_get_mesh(self._h, c_void_p(out.data_ptr())))
+            return out
         out = np.empty((self.nm,) * 3, dtype=np.float32)
         self._check(self._lib.cube_get_mesh(self._h, _ptr(out)))
         return out

@@ -742,9 +742,9 @@ int cube_stage_move(cube_sim* sim, float kfac, float dfac) {
   return CUBE_OK;
 }
 
-int cube_get_mesh(cube_sim* sim, float* host_dst) {
-  if (!sim || !host_dst) return CUBE_E_INVALID;
-  CUBE_GUARD(sim, { cube::copy_mesh_out(sim->s, host_dst, hipMemcpyDeviceToHost); });
+int cube_get_mesh(cube_sim* sim, float* dst) {
+  if (!sim || !dst) return CUBE_E_INVALID;
+  CUBE_GUARD(sim, { cube::copy_mesh_out(sim->s, dst, hipMemcpyDefault); });
   return CUBE_OK;
 }
 
@@ -958,17 +958,17 @@ int cube_get_state(cube_sim* sim, cube_state_view* out) {
     cube::require_particles(s);
     const int c = s.cur;
     const hipStream_t st = s.stream;
-    CUBE_HIP(hipMemcpyAsync(out->cnt, s.cnt[c], sizeof(uint32_t) * s.nc3, hipMemcpyDeviceToHost, st));
+    CUBE_HIP(hipMemcpyAsync(out->cnt, s.cnt[c], sizeof(uint32_t) * s.nc3, hipMemcpyDefault, st));
     for (int d = 0; d < 3; ++d) {
       CUBE_HIP(hipMemcpyAsync(static_cast<char*>(out->chi) + (size_t)d * s.n * s.nchi,
                               static_cast<char*>(s.chi[c]) + (size_t)d * s.capacity * s.nchi, (size_t)s.n * s.nchi,
-                              hipMemcpyDeviceToHost, st));
+                              hipMemcpyDefault, st));
       CUBE_HIP(hipMemcpyAsync(static_cast<char*>(out->nu) + (size_t)d * s.n * s.nnu,
                               static_cast<char*>(s.nu[c]) + (size_t)d * s.capacity * s.nnu, (size_t)s.n * s.nnu,
-                              hipMemcpyDeviceToHost, st));
+                              hipMemcpyDefault, st));
     }
-    CUBE_HIP(hipMemcpyAsync(out->vc, s.vc[c], sizeof(float) * 3 * s.nc3, hipMemcpyDeviceToHost, st));
-    CUBE_HIP(hipMemcpyAsync(out->vs, s.vs[c], sizeof(float) * s.nc3, hipMemcpyDeviceToHost, st));
+    CUBE_HIP(hipMemcpyAsync(out->vc, s.vc[c], sizeof(float) * 3 * s.nc3, hipMemcpyDefault, st));
+    CUBE_HIP(hipMemcpyAsync(out->vs, s.vs[c], sizeof(float) * s.nc3, hipMemcpyDefault, st));
     CUBE_HIP(hipStreamSynchronize(st));
     out->n = s.n;
     out->a = cube_scale_factor(sim);

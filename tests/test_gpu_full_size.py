@@ -1,6 +1,8 @@
 """The 2048^3-particle workload at full size, in the launch configuration the benchmark times
 (two warm-up steps, then the autotuned kernel variants). The FP64 oracle cannot run 8.6e9
-particles, so the checks are properties that hold at any size:
+particles; sampled coarse cells are checked code for code against the FP32 twin run on the
+particles and potential around them (test_full_size_sampled_cells_bit_exact), and the rest by
+properties that hold at any size:
 
 * mass: the coarse-cell counts sum to N exactly, after the initial conditions and after steps;
 * initial conditions: P(k) of the lowest shells follows the linear spectrum at a_init (Sec. 2.3.2,
@@ -128,3 +130,115 @@ def test_full_size_poisson_on_plane_waves(lib, variant):
     err = np.abs(got - want).max() / np.abs(want).max()
     print(f"variant {variant}: max |phi - exact| / max |phi| = {err:.2e}")
     assert err < 1e-5
+
+
+def _sub_box(st, centers, nc, rad):
+    """The state of the (2 rad + 1)^3 coarse cells around each centre (periodic), from a state held
+    in device tensors, as host twin.State objects in the sub-box's own cell order (x fastest)."""
+    import torch
+    from oracle import twin
+    cnt = st["cnt"].to(torch.int64)
+    off = torch.cumsum(cnt, 0) - cnt
+    w = 2 * rad + 1
+    out = []
+    for (cx, cy, cz) in centers:
+        d = np.arange(-rad, rad + 1)
+        gz, gy, gx = np.meshgrid((cz + d) % nc, (cy + d) % nc, (cx + d) % nc, indexing="ij")
+        cid = torch.from_numpy((gx + nc * (gy + nc * gz)).reshape(-1)).cuda()
+        c_cnt = cnt[cid].cpu().numpy()
+        c_off = off[cid].cpu().numpy()
+        idx = torch.from_numpy(np.concatenate([np.arange(o, o + c, dtype=np.int64) for o, c in zip(c_off, c_cnt)])).cuda()
+        chi = st["chi"][:, idx].cpu().numpy()
+        nu = st["nu"][:, idx].cpu().numpy()
+        vc = st["vc"][:, cid].cpu().numpy()
+        vs = st["vs"][cid].cpu().numpy()
+        out.append((twin.State(w, 1, 1, c_cnt.astype(np.uint32), chi.view(np.uint8), nu.view(np.int8), vc, vs),
+                    c_off))
+    return out
+
+
+def _fine_block(mesh, centers, nm, rad):
+    """The fine cells of the (2 rad + 1)^3 coarse cells around each centre (periodic), [z, y, x]."""
+    import torch
+    out = []
+    for (cx, cy, cz) in centers:
+        d = np.arange(-4 * rad, 4 * rad + 4)
+        iz = torch.from_numpy((4 * cz + d) % nm).cuda()
+        iy = torch.from_numpy((4 * cy + d) % nm).cuda()
+        ix = torch.from_numpy((4 * cx + d) % nm).cuda()
+        out.append(mesh[iz][:, iy][:, :, ix].cpu().numpy())
+    return out
+
+
+def test_full_size_sampled_cells_bit_exact(lib):
+    """Code-level parity at 2048^3, in the benchmark's launch configuration (warm-up steps, then
+    the autotuned variants): for sampled coarse cells -- among them the most crowded one and cells
+    whose particles sit beyond 2^32 in the state arrays -- the FP32 density of the cell's fine
+    cells after the deposit, and the cell's whole new content after the move (count, mean velocity,
+    decode scale, every particle's codes in storage order), equal the FP32 twin run on the 5^3
+    coarse cells around the cell (every particle that can reach the cell, and the potential the
+    GPU solved around them), bit for bit."""
+    import torch
+    from oracle import twin
+    torch.cuda.empty_cache()
+    cfg = synth.WORKLOADS[NAME]
+    need = lib.footprint(**cfg) + (8 << 30)  # the initial conditions' peak, the FFT scratch
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    nm, nc, n = cfg["nm_side"], cfg["nc_side"], cfg["np_side"] ** 3
+    assert cfg["x_bytes"] == 1 and cfg["v_bytes"] == 1
+    rad = 2
+    with lib.Sim(**cfg) as sim:
+        sim.init_ic()
+        sim.step(2)
+        sim.autotune()
+        sim.step(1)
+        _, kicks, drifts = sim.get_schedule()
+        j = sim.steps_done
+        kf, df = np.float32(-kicks[j] / 12.0), np.float32(drifts[j])
+        torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info()
+        if free < (56 << 30):  # one device copy of the state
+            pytest.skip(f"a device copy of the state needs 56 GiB, {free / 2**30:.0f} GiB free")
+        s0 = sim.get_state(device=True)
+        cnt = s0["cnt"].to(torch.int64)
+        crowded = int(torch.argmax(cnt))
+        g = np.random.default_rng(5)
+        cells = [crowded] + [int(c) for c in g.integers(0, nc**3, size=3)]
+        cells += [int(c) for c in g.integers(nc**3 * 3 // 4, nc**3, size=2)]  # offsets beyond 2^32
+        centers = [(c % nc, (c // nc) % nc, c // (nc * nc)) for c in cells]
+        subs0 = _sub_box(s0, centers, nc, rad)
+        assert int(cnt.sum()) == n
+        del s0, cnt
+        torch.cuda.empty_cache()
+        sim.stage_deposit()
+        dens = _fine_block(sim.get_mesh(device=True), centers, nm, rad)
+        sim.stage_solve()
+        phis = _fine_block(sim.get_mesh(device=True), centers, nm, rad)
+        torch.cuda.empty_cache()
+        sim.stage_move(kf, df)
+        s1 = sim.get_state(device=True)
+        subs1 = _sub_box(s1, centers, nc, 0)
+        del s1
+    w = 2 * rad + 1
+    ctr = rad + w * (rad + w * rad)
+    inv_mean = float(nm) ** 3 / (float(n) * 2.0 ** 21)
+    for (st0, off0), rho_gpu, phi, (st1, off1), c in zip(subs0, dens, phis, subs1, cells):
+        assert st1.cnt[0] >= 2  # a per-cell dispersion
+        # deposit: the fine cells of the centre cell receive mass only from the 3^3 cells around it
+        rho = twin.deposit_int(st0, 4 * w)
+        sl = slice(4 * rad, 4 * rad + 4)
+        want = (rho[sl, sl, sl].astype(np.float64) * inv_mean - 1.0).astype(np.float32)
+        assert np.array_equal(rho_gpu[sl, sl, sl], want), f"density of cell {c}"
+        # move: every particle that can arrive in the centre cell comes from the 3^3 cells around it,
+        # whose CIC and 4-point stencils stay inside the 5^3 block of potential
+        new = twin.move(st0, phi, kf, df, sigma_mode=twin.SIGMA_PER_CELL)
+        beg = int(np.sum(new.cnt[:ctr].astype(np.int64)))
+        m = int(new.cnt[ctr])
+        assert st1.cnt[0] == m, f"count of cell {c}"
+        assert np.array_equal(st1.chi, new.chi[:, beg:beg + m]), f"positions of cell {c}"
+        assert np.array_equal(st1.nu, new.nu[:, beg:beg + m]), f"velocities of cell {c}"
+        assert np.array_equal(st1.vc[:, 0], new.vc[:, ctr]) and st1.vs[0] == new.vs[ctr], f"statistics of cell {c}"
+        print(f"cell {c}: {m} particles from offset {off1[0]} bit-exact (density of its 64 fine cells too)")
+    assert max(int(o[0]) for _, o in subs1) > 2**32
