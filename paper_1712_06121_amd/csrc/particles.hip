@@ -27,6 +27,14 @@ namespace cube {
 namespace {
 
 constexpr int T = 4;            // coarse cells per tile side
+// tile offsets (x, y, z) of own cell s (x fastest), by shifts: s is never negative
+__device__ __forceinline__ void tile_xyz(int s, int& ox, int& oy, int& oz) {
+  static_assert(T == 4, "shifts assume four cells per side");
+  const unsigned u = (unsigned)s;
+  ox = (int)(u & 3u);
+  oy = (int)((u >> 2) & 3u);
+  oz = (int)(u >> 4);
+}
 constexpr int TC = T * T * T;   // own cells per tile
 constexpr int F = 4 * T;        // fine cells per tile side
 constexpr int PH = F + 6;       // potential tile side (3-cell halo)
@@ -523,7 +531,7 @@ __device__ __forceinline__ bool new_cell(float ln, float vd, uint32_t* flags, in
   float lw;
   if (ln >= -4.0f && ln < 8.0f && fabsf(vd) < 32768.0f) {
     k = ln < 0.0f ? -1 : (ln >= 4.0f ? 1 : 0);
-    lw = k == 0 ? ln : (k < 0 ? ln + 4.0f : ln - 4.0f);
+    lw = __builtin_fmaf(-4.0f, (float)k, ln);  // ln, ln + 4 or ln - 4, each one rounding
   } else {
     k = 0;
     lw = ln;
@@ -969,7 +977,8 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
     }
     gbase = (uint32_t)__shfl((int)gbase, leader, 64);
     if (active) {
-      const int ox = s % T, oy = (s / T) % T, oz = s / (T * T);
+      int ox, oy, oz;
+      tile_xyz(s, ox, oy, oz);
       const int nx = wrapi(g.cx0 + ox + m.k[0], a.nc), ny = wrapi(g.cy0 + oy + m.k[1], a.nc);
       const int nz = wrapi(g.cz0 + oz + m.k[2], a.nc);
       const int64_t cn = nx + (int64_t)a.nc * (ny + (int64_t)a.nc * nz);
@@ -1228,7 +1237,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       // (past the end the request repeats a particle of this chunk)
       if (c0 + 64u * NW < tot) locate(c0 + 64u * NW, sn, pn);
       load_at(pn);
-      const int ci = s % T, o1 = (s / T) % T, o2 = s / (T * T);
+      int ci, o1, o2;
+      tile_xyz(s, ci, o1, o2);
       float v[3];
       int k[3], cq[3];
       physics(active, s, ci, o1, o2, chc, nuc, v, k, cq);
@@ -1286,16 +1296,21 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
       } else {
         // Scatter: the rank inside the (new cell, source offset) slot is the number of the
         // particles before this one in storage order with the same (source cell, displacement).
-        // Within the chunk it comes from the lanes with the same key (one ballot per key bit);
-        // across chunks from the running count per key in LDS, which the chunks update strictly in
-        // storage order: chunk c waits until c chunks have been ranked (wavefronts of one
-        // workgroup are all resident, and chunk c - 1's wavefront never waits for chunk c, so the
-        // wait ends; it is also bounded, and one that gives up raises an error flag).
-        const int key = s * 27 + dcode;  // < 64 * 27, 11 bits
-        unsigned long long peers = __ballot(active);
+        // Within the chunk it comes from the lanes with the same key: the cell's lanes are one
+        // contiguous range, the displacement is matched with one ballot per bit of its code.
+        // Across chunks it comes from the running count per key in LDS, which the chunks update
+        // strictly in storage order: chunk c waits until c chunks have been ranked (wavefronts of
+        // one workgroup are all resident, and chunk c - 1's wavefront never waits for chunk c, so
+        // the wait ends; it is also bounded, and one that gives up raises an error flag).
+        const int key = s * 27 + dcode;
+        const uint32_t cbeg = pre[s], cend = pre[s + 1];
+        const int la = cbeg > c0 ? (int)(cbeg - c0) : 0;  // the cell's lanes: [la, cend - c0)
+        const uint32_t le = cend - c0;
+        unsigned long long peers =
+            __ballot(active) & (le >= 64u ? ~0ull : ((1ull << le) - 1ull)) & ~((1ull << la) - 1ull);
 #pragma unroll
-        for (int bt = 0; bt < 11; ++bt) {
-          const bool bit = (key >> bt) & 1;
+        for (int bt = 0; bt < 5; ++bt) {
+          const bool bit = (dcode >> bt) & 1;
           const unsigned long long bb = __ballot(active && bit);
           peers &= bit ? bb : ~bb;
         }
