@@ -148,6 +148,13 @@ int cube_set_two_level(cube_sim* sim, double r_s);
  * Errors: CUBE_E_INVALID. */
 int cube_debug_inject_flag(cube_sim* sim, int32_t step, uint32_t flag);
 
+/* For tests of the error path: the gradient-tile scatter ranks a tile's chunks in storage order,
+ * each chunk waiting (polling an LDS word) until the previous one is ranked; after `polls` polls
+ * (default 2^22, far beyond any legitimate wait) a chunk stops waiting and raises the count error
+ * (8), so the step fails with CUBE_E_STATE and is not applied. A small value forces that path.
+ * Errors: CUBE_E_INVALID (polls 0). */
+int cube_debug_set_turn_limit(cube_sim* sim, uint32_t polls);
+
 /* Adaptive time steps (Sec. 2.3.3: the step is bounded by the particles' largest velocity and
  * acceleration and by the expansion), chosen before the first step; eta_v = eta_a = eta_e = 0
  * returns to the fixed schedule. Each interval [a0, a1] of the kicks is the largest with

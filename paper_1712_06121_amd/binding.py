@@ -34,7 +34,8 @@ EXPORTED = [
     "cube_batch_box", "cube_batch_init_ic", "cube_batch_autotune", "cube_batch_step", "cube_batch_set_mode",
     "cube_footprint", "cube_get_cross_power", "cube_enable_pids", "cube_get_pids", "cube_set_pids",
     "cube_get_counts_u8", "cube_counts_from_u8", "cube_set_ic_parent", "cube_set_adaptive",
-    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag", "cube_get_power_noalloc", "cube_autotune_report", "cube_set_two_level",
+    "cube_get_adaptive_log", "cube_get_last_maxima", "cube_debug_inject_flag", "cube_debug_set_turn_limit",
+    "cube_get_power_noalloc", "cube_autotune_report", "cube_set_two_level",
     "cube_server_create", "cube_server_destroy", "cube_server_last_error", "cube_server_submit", "cube_server_poll",
     "cube_server_status", "cube_server_job_error", "cube_server_job", "cube_server_release", "cube_server_stats",
 ]
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cube_load_particles.argtypes = [sim_p, c_void_p, c_void_p, c_int64]
     lib.cube_step.argtypes = [sim_p, c_int32]
     lib.cube_debug_inject_flag.argtypes = [sim_p, c_int32, c_uint32]
+    lib.cube_debug_set_turn_limit.argtypes = [sim_p, c_uint32]
     lib.cube_set_two_level.argtypes = [sim_p, c_double]
     lib.cube_scale_factor.argtypes = [sim_p]
     lib.cube_scale_factor.restype = c_double
@@ -348,6 +350,11 @@ class Sim:
     def debug_inject_flag(self, step: int, flag: int):
         """Raise device error bits before the move of `step` (tests of the error path); -1: off."""
         self._check(self._lib.cube_debug_inject_flag(self._h, step, flag))
+
+    def debug_set_turn_limit(self, polls: int):
+        """Polls after which a gradient-tile scatter chunk stops waiting for its turn and raises
+        the count error (tests of that path); the default is 2^22."""
+        self._check(self._lib.cube_debug_set_turn_limit(self._h, polls))
 
     def get_power(self, nbins: int | None = None):
         nb = nbins or self.nm // 2

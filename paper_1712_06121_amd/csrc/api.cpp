@@ -690,6 +690,13 @@ int cube_debug_inject_flag(cube_sim* sim, int32_t step, uint32_t flag) {
   return CUBE_OK;
 }
 
+int cube_debug_set_turn_limit(cube_sim* sim, uint32_t polls) {
+  if (!sim || polls == 0u) return CUBE_E_INVALID;
+  sim->s.turn_limit = polls;
+  sim->s.config_gen++;  // captured step graphs hold the previous limit
+  return CUBE_OK;
+}
+
 double cube_scale_factor(const cube_sim* sim) {
   if (!sim) return 0.0;
   const cube::Sim& s = sim->s;

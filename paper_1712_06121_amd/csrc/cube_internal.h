@@ -170,6 +170,9 @@ struct Sim {
   // inject_step (-1: never)
   int inject_step = -1;
   uint32_t inject_flag = 0;
+  // polls of the gradient-tile scatter's ordered section before a chunk gives up waiting and
+  // raises the count error (tests of that path set it small)
+  uint32_t turn_limit = 1u << 22;
 
   // profiling: per-kernel event pairs recorded on the simulation's stream
   bool profiling = false;

@@ -413,6 +413,9 @@ struct MoveArgs {
   // adaptive time steps: when set, the count pass raises amax[0] to the largest |v|^2 after the
   // kick and amax[1] to the largest |t|^2 of the interpolated gradient (FP32 bit patterns)
   uint32_t* amax;
+  // gradient-tile scatter: polls of the LDS turn word after which a chunk stops waiting for its
+  // turn and raises the count error (the wait then ends whatever the other wavefronts do)
+  uint32_t turn_limit;
 };
 
 
@@ -1336,7 +1339,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
           while (__hip_atomic_load(&turn[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != chunk &&
                  __hip_atomic_load(&turn[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u) {
             __builtin_amdgcn_s_sleep(2);
-            if (++spins == (1u << 22)) {
+            if (++spins >= a.turn_limit) {
               if (lane == 0) {
                 __hip_atomic_store(&turn[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 set_flag(a.flags, FLAG_COUNT);
@@ -1835,6 +1838,7 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   // step maxima for adaptive time steps (a small fill kernel clears them: no memset node in
   // captured graphs, although adaptive simulations are never captured)
   a.amax = (mode == 0 && s.amax) ? s.amax : nullptr;
+  a.turn_limit = s.turn_limit;
   if (a.amax) {
     k_clear_u32<<<1, 64, 0, st>>>(s.amax, 2);
     CUBE_HIP(hipGetLastError());

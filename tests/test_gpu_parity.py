@@ -225,6 +225,32 @@ def test_move_crowded_cell_bit_exact(Sim, move_variant):
     assert_state_equal(got, exp, f"crowded cell, move variant {move_variant}")
 
 
+def test_scatter_wait_limit_raises_error(Sim):
+    """The gradient-tile scatter's ordered section is a bounded wait: with the bound forced down
+    to one poll, chunks of a crowded tile give up waiting, the move reports the count error and
+    is not applied, and with the default bound the same move is bit-exact."""
+    from paper_1712_06121_amd import CubeError
+    nm, n = 32, 100000
+    x, v = synth.particle_cloud(17, n, nm, vscale=0.5, clump_frac=0.9, n_clumps=1, clump_radius=0.7)
+    st = twin.load(x, v, nm // 4, 1, 1, 1)
+    phi = synth.smooth_potential(9, nm, amp=0.5)
+    kf, df = np.float32(-1.3 / 12.0), np.float32(0.5)
+    exp = twin.move(st, phi, kf, df, sigma_mode=1)
+    with Sim(np_for(nm), nm, 100.0, sigma_mode=1, capacity=n) as sim:
+        sim.set_state(st.cnt, st.chi, st.nu, st.vc, st.vs)
+        sim.set_variant(move_variant=1)
+        sim.set_mesh(phi)
+        sim.debug_set_turn_limit(1)
+        with pytest.raises(CubeError) as e:
+            sim.stage_move(kf, df)
+        assert e.value.code == -8  # CUBE_E_STATE: the count changed during the move
+        assert_state_equal(sim.get_state(), st, "state after the failed move")
+        sim.debug_set_turn_limit(1 << 22)
+        sim.set_mesh(phi)
+        sim.stage_move(kf, df)
+        assert_state_equal(sim.get_state(), exp, "move after the failed one")
+
+
 def test_cfl_violation_reported(Sim):
     from paper_1712_06121_amd import CubeError
     nm, nc, n = 64, 16, 5000
