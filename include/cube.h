@@ -342,11 +342,10 @@ int cube_set_variant(cube_sim* sim, const cube_variant* v);
 /* ---- ensembles of independent boxes ----------------------------------------------------------
  * A batch holds nbox simulations (box i created from params[i]; sizes, codecs and cosmologies may
  * differ, n_steps must be equal), each on its own HIP stream created by the batch. One step of the
- * whole ensemble is captured once into a HIP graph with one independent branch per box and
- * replayed for every step (the kick and drift factors are read on the device from each box's
- * schedule), so the boxes' kernels overlap on the GPU and the host makes one launch per step.
- * Every box evolves exactly as it would alone: the results are bit-identical to stepping it by
- * itself with cube_step. */
+ * whole ensemble is captured once into a HIP graph and replayed for every step (the kick and drift
+ * factors are read on the device from each box's schedule), so the host makes one launch per
+ * step. Every box evolves exactly as it would alone: the results are bit-identical to stepping it
+ * by itself with cube_step. */
 typedef struct cube_batch cube_batch;
 
 /* `stream`: hipStream_t on which the step graphs are launched (NULL: a stream the batch creates,
@@ -362,9 +361,18 @@ int32_t cube_batch_size(const cube_batch* b);
  * (state, density, power, ...) apply to it; stepping a box alone makes the batch refuse to step
  * until the boxes are at the same step again (CUBE_E_STATE). */
 cube_sim* cube_batch_box(cube_batch* b, int32_t i);
-/* How cube_batch_step launches the boxes' kernels: 0 (default) one captured graph per step for
- * the whole ensemble; 1 each box's kernels enqueued directly on its own stream, box after box (no
- * graph). Both give the same results. Errors: CUBE_E_INVALID. */
+/* How cube_batch_step launches the boxes' kernels:
+ *   0 (default) one captured graph per step with an independent branch of kernels per box;
+ *   1 each box's kernels enqueued directly on its own stream, box after box (no graph);
+ *   2 one captured graph per step in which every stage (deposit, each FFT pass, count, link,
+ *     block scan, finalize, scatter, step end) is one launch over all boxes: the kernels find
+ *     their box and tile in device tables of per-box arguments, built when the graph is captured
+ *     (a few kB per box). Boxes that use different kernels for a stage (FFT size and variants,
+ *     deposit workgroup size, move-pass kernel, codec) get one launch each for it. Needs
+ *     single-level solves in every box.
+ * All modes give the same results. Changing the mode drops the captured graphs (after waiting for
+ * the batch's stream). Errors: CUBE_E_INVALID (unknown mode; mode 2 with a box whose two-level
+ * force is on). */
 int cube_batch_set_mode(cube_batch* b, int32_t mode);
 /* Initial conditions of every box (cube_init_ic on each). */
 int cube_batch_init_ic(cube_batch* b);

@@ -582,7 +582,9 @@ class Batch:
     def step(self, k: int = 1) -> int:
         return self._check(self._lib.cube_batch_step(self._h, k))
 
-    GRAPH, STREAMS = 0, 1
+    # 0: graph with a branch per box; 1: each box's kernels on its own stream; 2: graph with one
+    # launch per stage over all boxes
+    GRAPH, STREAMS, ENSEMBLE = 0, 1, 2
 
     def set_mode(self, mode: int):
         self._check(self._lib.cube_batch_set_mode(self._h, mode))

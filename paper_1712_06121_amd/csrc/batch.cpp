@@ -2,14 +2,17 @@
 //
 // A batch owns one simulation per box, each on its own HIP stream. One step of the whole ensemble
 // (deposit, five-pass Poisson solve, count / link / scatter move passes and a step-counter bump
-// per box) is captured once into a HIP graph in which every box is an independent branch, so the
-// boxes' kernels overlap on the device and the host launches one graph per step. The kick and drift
-// factors of each step are read on the device from the box's schedule table, so the same graph
-// is replayed for every step; two graphs are kept, one per parity of the double-buffered state.
+// per box) is captured once into a HIP graph and replayed for every step: the kick and drift
+// factors of each step are read on the device from the box's schedule table, and two graphs are
+// kept, one per parity of the double-buffered state. In the graph either every box is an
+// independent branch of its own kernels (mode 0), or every stage is one launch over all boxes
+// (mode 2: the kernels find their box and tile in a table of per-box arguments, so the tiles of
+// small boxes fill the GPU beside those of large ones and a step is a few dozen launches).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <map>
+#include <memory>
 #include <tuple>
 
 #include "cube_internal.h"
@@ -21,7 +24,10 @@ struct cube_batch {
   hipEvent_t fork = nullptr;
   hipStream_t main = nullptr;
   bool own_main = false;  // graphs cannot be captured on the null stream: the batch then makes its own
-  int mode = 0;           // 0: one captured graph per step; 1: kernels enqueued box by box on the box streams
+  // 0: one captured graph per step, a branch per box; 1: kernels enqueued box by box on the box
+  // streams; 2: one captured graph per step, one launch per stage over all boxes
+  int mode = 0;
+  std::unique_ptr<cube::EnsembleStep> table[2];  // mode 2: the launches and tables of each parity
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::vector<int> gens;  // each box's config_gen when the graphs were captured
@@ -65,21 +71,47 @@ void destroy_graphs(cube_batch& b) {
     if (b.graph[p]) (void)hipGraphDestroy(b.graph[p]);
     b.exec[p] = nullptr;
     b.graph[p] = nullptr;
+    b.table[p].reset();
   }
+}
+
+// mode 2: the stages of one ensemble step from parity `par`, each one launch (per kernel variant)
+// over every box, in the order of enqueue_graph_step
+std::unique_ptr<EnsembleStep> plan_table_step(cube_batch& b) {
+  std::vector<Sim*> ss;
+  for (cube_sim* x : b.boxes) ss.push_back(&x->s);
+  auto es = std::make_unique<EnsembleStep>();
+  ensemble_deposit(*es, ss);
+  ensemble_solve(*es, ss);
+  for (Sim* s : ss)
+    if (s->inject_step >= 0) {
+      const uint32_t f = s->inject_flag;
+      const int at = s->inject_step;
+      es->launches.push_back([s, f, at](hipStream_t st) { launch_raise_flag(*s, st, f, true, at); });
+    }
+  ensemble_move(*es, ss);
+  ensemble_step_end(*es, ss);
+  es->upload();
+  return es;
 }
 
 // capture one ensemble step starting from state parity `par` (every box has cur == par)
 void build_graph(cube_batch& b, int par) {
+  if (b.mode == 2 && !b.table[par]) b.table[par] = plan_table_step(b);
   CUBE_HIP(hipStreamBeginCapture(b.main, hipStreamCaptureModeRelaxed));
   try {
-    CUBE_HIP(hipEventRecord(b.fork, b.main));
-    for (size_t i = 0; i < b.boxes.size(); ++i) {
-      Sim& s = b.boxes[i]->s;
-      CUBE_HIP(hipStreamWaitEvent(b.streams[i], b.fork, 0));
-      enqueue_graph_step(s, b.streams[i]);
-      s.cur = par;  // the capture flipped the host-side parity; replays flip it instead
-      CUBE_HIP(hipEventRecord(b.joins[i], b.streams[i]));
-      CUBE_HIP(hipStreamWaitEvent(b.main, b.joins[i], 0));
+    if (b.mode == 2) {
+      b.table[par]->enqueue(b.main);
+    } else {
+      CUBE_HIP(hipEventRecord(b.fork, b.main));
+      for (size_t i = 0; i < b.boxes.size(); ++i) {
+        Sim& s = b.boxes[i]->s;
+        CUBE_HIP(hipStreamWaitEvent(b.streams[i], b.fork, 0));
+        enqueue_graph_step(s, b.streams[i]);
+        s.cur = par;  // the capture flipped the host-side parity; replays flip it instead
+        CUBE_HIP(hipEventRecord(b.joins[i], b.streams[i]));
+        CUBE_HIP(hipStreamWaitEvent(b.main, b.joins[i], 0));
+      }
     }
   } catch (...) {
     hipGraph_t g = nullptr;
@@ -389,9 +421,19 @@ cube_sim* cube_batch_box(cube_batch* b, int32_t i) {
 
 int cube_batch_set_mode(cube_batch* b, int32_t mode) {
   if (!b) return CUBE_E_INVALID;
-  if (mode != 0 && mode != 1) {
-    b->last_error = "batch mode must be 0 (graph) or 1 (streams)";
+  if (mode < 0 || mode > 2) {
+    b->last_error = "batch mode must be 0 (graph of per-box branches), 1 (streams) or 2 (graph of ensemble launches)";
     return CUBE_E_INVALID;
+  }
+  if (mode == 2)
+    for (size_t i = 0; i < b->boxes.size(); ++i)
+      if (b->boxes[i]->s.two_level_rs > 0.0) {
+        b->last_error = "box " + std::to_string(i) + ": ensemble launches need single-level solves";
+        return CUBE_E_INVALID;
+      }
+  if (mode != b->mode) {
+    if (b->main) (void)hipStreamSynchronize(b->main);
+    cube::destroy_graphs(*b);
   }
   b->mode = mode;
   return CUBE_OK;
@@ -441,9 +483,11 @@ int cube_batch_step(cube_batch* b, int32_t k) {
   CUBE_BATCH_GUARD(b, {
     std::vector<cube::Sim*> ss;
     for (cube_sim* x : b->boxes) ss.push_back(&x->s);
-    for (cube::Sim* s : ss) {
-      cube::require_particles(*s);
-      if (s->adaptive) throw Error{CUBE_E_INVALID, "adaptive time steps are not supported in a batch"};
+    for (size_t i = 0; i < ss.size(); ++i) {
+      cube::require_particles(*ss[i]);
+      if (ss[i]->adaptive) throw Error{CUBE_E_INVALID, "adaptive time steps are not supported in a batch"};
+      if (b->mode == 2 && ss[i]->two_level_rs > 0.0)
+        throw Error{CUBE_E_INVALID, "box " + std::to_string(i) + ": ensemble launches need single-level solves"};
     }
     const int done = ss[0]->steps_done;
     for (cube::Sim* s : ss)
@@ -473,7 +517,7 @@ int cube_batch_step(cube_batch* b, int32_t k) {
         break;
       }
       for (cube::Sim* s : ss) s->phases.push_back({(uint32_t)s->steps_done + 2u, s->cur, s->steps_done, true});
-      if (b->mode == 0) {
+      if (b->mode != 1) {
         cube::check_graphs(*b);
         const int par = ss[0]->cur;
         if (!b->exec[par]) cube::build_graph(*b, par);
@@ -488,7 +532,7 @@ int cube_batch_step(cube_batch* b, int32_t k) {
         for (cube::Sim* s : ss) s->steps_done++;  // launch_move flipped the parity already
       }
     }
-    if (b->mode != 0)
+    if (b->mode == 1)
       for (size_t bi = 0; bi < ss.size(); ++bi) {
         CUBE_HIP(hipEventRecord(b->joins[bi], b->streams[bi]));
         CUBE_HIP(hipStreamWaitEvent(b->main, b->joins[bi], 0));

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -42,6 +43,27 @@ enum : uint32_t {
 __host__ __device__ inline unsigned xcd_block(unsigned b, unsigned n) {
   const unsigned per = n / 8, rem = n % 8, x = b % 8, i = b / 8;
   return x * per + (x < rem ? x : rem) + i;
+}
+
+// ---- ensemble launches: one launch of a stage over several boxes ----------------------------
+// The launch's logical workgroups (XCD-contiguous order) are cut into consecutive ranges, box b
+// owning [first[b], first[b + 1]); args[b] holds box b's kernel arguments. The box of a workgroup
+// is found by bisection over first[] (wave-uniform scalar reads).
+template <class A>
+struct BoxTable {
+  const A* args;
+  const uint32_t* first;  // nbox + 1 entries, first[0] = 0, first[nbox] = workgroups of the launch
+  int nbox;
+};
+
+__device__ __forceinline__ int box_of(const uint32_t* __restrict__ first, int nbox, unsigned l) {
+  int lo = 0, hi = nbox;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= l) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
 // ---- FFT plan: one cubic size N, half-complex padded layout --------------------------------
@@ -251,6 +273,46 @@ void launch_power_finish(Sim& s, int nbins, double* k, double* pk, double* nmode
 // device address of the allocation-free entry point's fixed shell-sum array on device `dev`
 // (looked up once per device; noalloc.hip)
 double* noalloc_scratch(int dev);
+
+}  // namespace cube
+
+namespace cube {
+
+// ---- ensemble steps: one launch per stage over every box (batch.cpp) -------------------------
+// The launches of one step of an ensemble, planned from the boxes' current state parity. Their
+// argument tables are staged on the host while the launches are planned and uploaded to one device
+// buffer before the first launch; a launch finds its tables at the buffer's base plus an offset.
+struct EnsembleStep {
+  std::vector<char> staged;                               // host copy of every table
+  char* dbase = nullptr;                                  // device copy (owned)
+  std::vector<std::function<void(hipStream_t)>> launches;  // the step's launches, in order
+  size_t put(const void* p, size_t bytes);                // stages a table; returns its offset
+  template <class T>
+  size_t put(const std::vector<T>& v) {
+    return put(v.data(), v.size() * sizeof(T));
+  }
+  template <class T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(dbase + off);
+  }
+  void upload();  // allocates the device buffer and copies the staged tables (synchronous)
+  void enqueue(hipStream_t st) const {
+    for (const auto& f : launches) f(st);
+  }
+  EnsembleStep() = default;
+  EnsembleStep(const EnsembleStep&) = delete;
+  EnsembleStep& operator=(const EnsembleStep&) = delete;
+  ~EnsembleStep();
+};
+// the stages of one step (every box at the same parity, single-level solves, fixed schedules):
+// deposits grouped by kernel variant (particles.hip); Poisson solves grouped by mesh size and FFT
+// variants (fft.hip); count passes grouped by kernel, then link, block scan and finalize of every
+// box, then scatter passes grouped by kernel (particles.hip); the step-counter bump and failure
+// record of every box (particles.hip)
+void ensemble_deposit(EnsembleStep& es, const std::vector<Sim*>& boxes);
+void ensemble_solve(EnsembleStep& es, const std::vector<Sim*>& boxes);
+void ensemble_move(EnsembleStep& es, const std::vector<Sim*>& boxes);
+void ensemble_step_end(EnsembleStep& es, const std::vector<Sim*>& boxes);
 
 }  // namespace cube
 

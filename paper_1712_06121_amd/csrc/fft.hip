@@ -13,6 +13,9 @@
 //            inverse z transform are fused into one pass, so the solve costs five passes over
 //            the mesh: x, y, z+G+z^-1, y^-1, x^-1.
 // All passes work in place on one buffer of N x N rows of pitch_c complex values.
+#include <map>
+#include <tuple>
+
 #include "cube_internal.h"
 
 namespace cube {
@@ -199,15 +202,15 @@ struct RowCfg {
 };
 
 template <int N>
-__global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int64_t pitch_f,
-                                                  const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_x_r2c_rows(float* __restrict__ data, int64_t pitch_f, const float2* __restrict__ tw,
+                                               const unsigned lb) {
   constexpr int H = RowCfg<N>::H, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
   __shared__ float2 lds[NL * H];
   // the first quarter of the twiddle table in LDS: the stages then make no global read, whose
   // latency every stage would otherwise wait for
   __shared__ float2 twq[N / 4];
   for (int i = threadIdx.x; i < N / 4; i += BLOCK) twq[i] = tw[i];
-  const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NL;
+  const int64_t row0 = (int64_t)lb * NL;
   constexpr int F4 = N / 4;
   constexpr int LPT = (NL * F4 + BLOCK - 1) / BLOCK;
   float4 stage[LPT];
@@ -245,14 +248,14 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int
 }
 
 template <int N>
-__global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int64_t pitch_f,
-                                                  const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_x_c2r_rows(float* __restrict__ data, int64_t pitch_f, const float2* __restrict__ tw,
+                                               const unsigned lb) {
   constexpr int H = N / 2, NL = RowCfg<N>::NL, BLOCK = RowCfg<N>::BLOCK;
   constexpr int LS = H + 1;
   __shared__ float2 lds[NL * LS];
   __shared__ float2 twq[N / 4];  // the first quarter of the twiddle table
   for (int i = threadIdx.x; i < N / 4; i += BLOCK) twq[i] = tw[i];
-  const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * NL;
+  const int64_t row0 = (int64_t)lb * NL;
   constexpr int LPT = (NL * LS + BLOCK - 1) / BLOCK;
   float2 stage[LPT];
 #pragma unroll
@@ -289,6 +292,33 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_x_r2c(float* __restrict__ data, int64_t pitch_f,
+                                                  const float2* __restrict__ tw) {
+  fft_x_r2c_rows<N>(data, pitch_f, tw, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_x_c2r(float* __restrict__ data, int64_t pitch_f,
+                                                  const float2* __restrict__ tw) {
+  fft_x_c2r_rows<N>(data, pitch_f, tw, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// the x passes of several meshes of one size in one launch: per workgroups of each mesh, in order
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_x_r2c_boxes(float* const* __restrict__ data, int64_t pitch_f,
+                                                        const float2* __restrict__ tw, unsigned per) {
+  const unsigned l = xcd_block(blockIdx.x, gridDim.x);
+  fft_x_r2c_rows<N>(data[l / per], pitch_f, tw, l % per);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_fft_x_c2r_boxes(float* const* __restrict__ data, int64_t pitch_f,
+                                                        const float2* __restrict__ tw, unsigned per) {
+  const unsigned l = xcd_block(blockIdx.x, gridDim.x);
+  fft_x_c2r_rows<N>(data[l / per], pitch_f, tw, l % per);
+}
+
 // ---- y / z passes: blocks of BX columns ------------------------------------------------------
 // BX: complex columns per workgroup (4 or 8 for N >= 1024, 8 or 16 below: 16 needs N <= 512 to
 // fit LDS). The padding of the rows leaves room for the widest.
@@ -323,10 +353,13 @@ struct ColGeom {
   int cb_r;  // column blocks per layout block: block cb starts at (cb / cb_r) cb_s + (cb % cb_r) BX
 };
 
+// one column block; lb: the block's logical index in the pass over one mesh, gx x gy blocks
+// (column blocks x other indices)
 template <int N, int MODE, int BX>
-__global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2* __restrict__ src, float2* __restrict__ dst,
-                                                                 ColGeom gs, ColGeom gt,
-                                                                 const float2* __restrict__ tw, ColArgs a) {
+__device__ __forceinline__ void fft_col_block(const float2* __restrict__ src, float2* __restrict__ dst,
+                                              const ColGeom& gs, const ColGeom& gt, const float2* __restrict__ tw,
+                                              const ColArgs& a, const unsigned lb, const unsigned gx,
+                                              const unsigned gy) {
   constexpr int BLOCK = ColCfg<N, BX>::BLOCK;
   __shared__ float2 lds[N * BX];
   // the first quarter of the twiddle table and (z pass) the squared wavenumbers, in LDS: the
@@ -336,23 +369,21 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
   for (int i = threadIdx.x; i < N / 4; i += BLOCK) twq[i] = tw[i];
   if constexpr (MODE == COL_GREEN)
     for (int i = threadIdx.x; i < N; i += BLOCK) k2s[i] = a.k2[i];
-  const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
-  const unsigned lb = a.order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
   int cb, o;
-  const unsigned paired = (gridDim.x - 1) * gridDim.y;
+  const unsigned paired = (gx - 1) * gy;
   if (a.order == 2 && lb < paired) {
     // groups of 2 x 2 (column block, other index): four consecutive blocks of one XCD cover whole
     // 128-byte lines both in the mesh (neighbouring column blocks) and in the scratch layout
     // (neighbouring other indices); the last column block (Nyquist column) comes after
-    const unsigned g = lb >> 2, r = lb & 3, hc = (gridDim.x - 1) / 2;
+    const unsigned g = lb >> 2, r = lb & 3, hc = (gx - 1) / 2;
     cb = 2 * (g % hc) + (r & 1);
     o = 2 * (g / hc) + (r >> 1);
   } else if (a.order == 2) {
-    cb = gridDim.x - 1;
+    cb = gx - 1;
     o = lb - paired;
   } else {
-    cb = lb % gridDim.x;
-    o = lb / gridDim.x;
+    cb = lb % gx;
+    o = lb / gx;
   }
   const int64_t base = (int64_t)o * gs.o_s + (int64_t)(cb / gs.cb_r) * gs.cb_s + (int64_t)(cb % gs.cb_r) * BX;
   const int64_t tstride = gs.t_s;
@@ -476,6 +507,35 @@ __global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2
   }
 }
 
+template <int N, int MODE, int BX>
+__global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                                 ColGeom gs, ColGeom gt,
+                                                                 const float2* __restrict__ tw, ColArgs a) {
+  const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
+  const unsigned lb = a.order ? xcd_block(bid, gridDim.x * gridDim.y) : bid;
+  fft_col_block<N, MODE, BX>(src, dst, gs, gt, tw, a, lb, gridDim.x, gridDim.y);
+}
+
+// a y or z pass over several meshes of one size in one launch: gx x gy workgroups per mesh, in
+// order; each mesh has its own source, destination and Green's constant
+struct ColBox {
+  const float2* src;
+  float2* dst;
+  float gconst;
+};
+
+template <int N, int MODE, int BX>
+__global__ __launch_bounds__((ColCfg<N, BX>::BLOCK)) void k_fft_col_boxes(const ColBox* __restrict__ boxes, ColGeom gs,
+                                                                       ColGeom gt, const float2* __restrict__ tw,
+                                                                       ColArgs a, unsigned gx, unsigned gy) {
+  const unsigned per = gx * gy;
+  const unsigned l = a.order ? xcd_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const ColBox& m = boxes[l / per];
+  ColArgs ab = a;
+  ab.gconst = m.gconst;
+  fft_col_block<N, MODE, BX>(m.src, m.dst, gs, gt, tw, ab, l % per, gx, gy);
+}
+
 // ---- host dispatch ---------------------------------------------------------------------------
 template <int N>
 void run_x(const FFTPlan& pl, float* data, bool forward, hipStream_t st) {
@@ -517,16 +577,21 @@ void run_col_bx(const FFTPlan& pl, const float* src, int ls, float* dst, int ld,
 }
 
 // a y or z pass from layout ls to layout ld (MESH or ZSCRATCH) with column blocks of width bx
+// workgroup order of a y or z pass: passes on the mesh along y and passes on the scratch layout:
+// XCD-contiguous ranges (neighbouring column blocks share 128-byte lines in one L2); y passes
+// between the layouts: 2 x 2 groups when the paired column blocks are even in number; z passes on
+// the mesh: tunable
+inline int col_order(const FFTPlan& pl, int n, int ls, int ld, int axis, int bx) {
+  const int ncb = (n / 2) / bx + 1;
+  if (ls != ld) return ((ncb - 1) % 2 == 0) ? 2 : 1;
+  return (axis == 1 || ls == ZSCRATCH) ? 1 : pl.zorder;
+}
+
 template <int N, int MODE>
 void run_col(const FFTPlan& pl, const float* src, int ls, float* dst, int ld, int axis, const ColArgs& a0,
              hipStream_t st, int bx) {
   ColArgs a = a0;
-  // passes on the mesh along y and passes on the scratch layout: XCD-contiguous ranges
-  // (neighbouring column blocks share 128-byte lines in one L2); y passes between the layouts: 2 x 2
-  // groups when the paired column blocks are even in number; z passes on the mesh: tunable
-  const int ncb = (N / 2) / bx + 1;
-  if (ls != ld) a.order = ((ncb - 1) % 2 == 0) ? 2 : 1;
-  else a.order = (axis == 1 || ls == ZSCRATCH) ? 1 : pl.zorder;
+  a.order = col_order(pl, N, ls, ld, axis, bx);
   if constexpr (N < 1024) {
     if (bx == 16) {
       run_col_bx<N, MODE, 16>(pl, src, ls, dst, ld, axis, a, st);
@@ -594,6 +659,77 @@ void ic_n(const FFTPlan& pl, const float* wk, float* out, const float* tab, int 
   run_col<N, COL_PSI>(pl, wk, out, 2, a, st);
   run_col<N, COL_INV>(pl, out, out, 1, a, st);
   run_x<N>(pl, out, false, st);
+}
+
+// ---- ensemble solves: each pass one launch over several meshes of one size --------------------
+template <int N>
+void run_x_boxes(const FFTPlan& pl, float* const* data, unsigned nbox, bool forward, hipStream_t st) {
+  const unsigned per = (unsigned)((int64_t)N * N / RowCfg<N>::NL);
+  if (forward)
+    k_fft_x_r2c_boxes<N><<<nbox * per, RowCfg<N>::BLOCK, 0, st>>>(data, (int64_t)pl.row_floats(), pl.tw, per);
+  else
+    k_fft_x_c2r_boxes<N><<<nbox * per, RowCfg<N>::BLOCK, 0, st>>>(data, (int64_t)pl.row_floats(), pl.tw, per);
+  CUBE_HIP(hipGetLastError());
+}
+
+template <int N, int MODE, int BX>
+void run_col_boxes_bx(const FFTPlan& pl, const ColBox* boxes, unsigned nbox, int ls, int ld, int axis,
+                      const ColArgs& a, hipStream_t st) {
+  const unsigned ncb = (N / 2) / BX + 1;
+  k_fft_col_boxes<N, MODE, BX><<<nbox * ncb * N, ColCfg<N, BX>::BLOCK, 0, st>>>(
+      boxes, col_geom<N, BX>(pl, ls, axis), col_geom<N, BX>(pl, ld, axis), pl.tw, a, ncb, (unsigned)N);
+  CUBE_HIP(hipGetLastError());
+}
+
+template <int N, int MODE>
+void run_col_boxes(const FFTPlan& pl, const ColBox* boxes, unsigned nbox, int ls, int ld, int axis,
+                   const ColArgs& a0, hipStream_t st, int bx) {
+  ColArgs a = a0;
+  a.order = col_order(pl, N, ls, ld, axis, bx);
+  if constexpr (N < 1024) {
+    if (bx == 16) {
+      run_col_boxes_bx<N, MODE, 16>(pl, boxes, nbox, ls, ld, axis, a, st);
+      return;
+    }
+  } else {
+    if (bx == 4) {
+      run_col_boxes_bx<N, MODE, 4>(pl, boxes, nbox, ls, ld, axis, a, st);
+      return;
+    }
+  }
+  run_col_boxes_bx<N, MODE, 8>(pl, boxes, nbox, ls, ld, axis, a, st);
+}
+
+// the Poisson solves of boxes whose meshes have size N and the same FFT variants: the five passes
+// of solve_n, each over all of them; per box its mesh, scratch copy and Green's constant
+template <int N>
+void solve_boxes_n(EnsembleStep& es, const std::vector<Sim*>& g) {
+  const FFTPlan pl = g[0]->mesh_plan;  // row pitch, variants and the (size-only) twiddle and k^2 tables
+  const bool zs = pl.zlayout && pl.zscratch;
+  std::vector<float*> data;
+  std::vector<ColBox> yf, zp, yi;
+  for (Sim* s : g) {
+    float2* m = reinterpret_cast<float2*>(s->mesh);
+    float2* z = zs ? s->mesh_plan.zscratch : m;
+    const float gc = gconst(*s);
+    data.push_back(s->mesh);
+    yf.push_back(ColBox{m, z, gc});
+    zp.push_back(ColBox{z, z, gc});
+    yi.push_back(ColBox{z, m, gc});
+  }
+  const size_t od = es.put(data), oyf = es.put(yf), ozp = es.put(zp), oyi = es.put(yi);
+  const unsigned nb = (unsigned)g.size();
+  const EnsembleStep* e = &es;
+  es.launches.push_back([=](hipStream_t st) {
+    const ColArgs a{pl.k2, 0.f, nullptr, nullptr, 0, N / 2, 0, CoarseTerm{}};
+    float* const* d = e->at<float*>(od);
+    const int lz = zs ? ZSCRATCH : MESH;
+    run_x_boxes<N>(pl, d, nb, true, st);
+    run_col_boxes<N, COL_FWD>(pl, e->at<ColBox>(oyf), nb, MESH, lz, 1, a, st, pl.colbx);
+    run_col_boxes<N, COL_GREEN>(pl, e->at<ColBox>(ozp), nb, lz, lz, 2, a, st, zs ? pl.zbx : pl.colbx);
+    run_col_boxes<N, COL_INV>(pl, e->at<ColBox>(oyi), nb, lz, MESH, 1, a, st, pl.colbx);
+    run_x_boxes<N>(pl, d, nb, false, st);
+  });
 }
 
 #define CUBE_FFT_DISPATCH(n, CALL)                        \
@@ -866,6 +1002,22 @@ void fft_solve_poisson(const FFTPlan& pl, float* data, float gconst, hipStream_t
 #define CUBE_CALL(N) solve_n<N>(pl, data, gconst, st, evs, ct)
   CUBE_FFT_DISPATCH(pl.n, CUBE_CALL)
 #undef CUBE_CALL
+}
+
+void ensemble_solve(EnsembleStep& es, const std::vector<Sim*>& boxes) {
+  // boxes grouped by mesh size, scratch layout, column widths and z-pass order
+  std::map<std::tuple<int, int, int, int, int>, std::vector<Sim*>> groups;
+  for (Sim* s : boxes) {
+    if (s->two_level_rs > 0.0)
+      throw Error{CUBE_E_INVALID, "ensemble launches need single-level solves (two-level force switched on)"};
+    const FFTPlan& pl = s->mesh_plan;
+    groups[std::make_tuple(pl.n, (pl.zlayout && pl.zscratch) ? 1 : 0, pl.colbx, pl.zbx, pl.zorder)].push_back(s);
+  }
+  for (const auto& kv : groups) {
+#define CUBE_CALL(N) solve_boxes_n<N>(es, kv.second)
+    CUBE_FFT_DISPATCH(std::get<0>(kv.first), CUBE_CALL)
+#undef CUBE_CALL
+  }
 }
 
 void fft_forward_3d(const FFTPlan& pl, float* data, hipStream_t st) {

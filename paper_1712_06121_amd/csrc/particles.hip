@@ -212,7 +212,7 @@ __device__ __forceinline__ int slot_of(int p) { return ((p % NSLOT) + NSLOT) % N
 // to a rolling set of NSLOT fine planes in LDS. After layer sz, planes up to 4 sz + 2 receive no
 // more mass: they are converted once to FP32 delta, written, and their slots reused.
 template <int NCHI, int BLK>
-__global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
+__device__ __forceinline__ void deposit_column(const DepArgs& a, const unsigned lb) {
   using CT = chi_t<NCHI>;
   constexpr int SH = 8 * NCHI - 1;
   __shared__ unsigned long long rho[NSLOT * DF * DF];
@@ -224,8 +224,8 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
   constexpr int NOWN = 1024;
   static_assert(DRC < 256, "cell indices fit a byte");
   __shared__ uint8_t owner[NOWN];
-  const unsigned lb = xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-  const unsigned bxy = lb % gridDim.x, bz = lb / gridDim.x;
+  const unsigned cols = (unsigned)(a.nt * a.nt);
+  const unsigned bxy = lb % cols, bz = lb / cols;
   const int cx0 = (bxy % a.nt) * DTX, cy0 = (bxy / a.nt) * DTX;
   const int cz0 = bz * a.zc;
   const int cz1 = min(cz0 + a.zc, a.nc);
@@ -362,6 +362,19 @@ __global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int NCHI, int BLK>
+__global__ __launch_bounds__(BLK) void k_deposit(DepArgs a) {
+  deposit_column<NCHI, BLK>(a, xcd_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y));
+}
+
+// every box of an ensemble in one launch (a box's workgroups: its columns times its z chunks)
+template <int NCHI, int BLK>
+__global__ __launch_bounds__(BLK) void k_deposit_boxes(BoxTable<DepArgs> t) {
+  const unsigned l = xcd_block(blockIdx.x, gridDim.x);
+  const int b = box_of(t.first, t.nbox, l);
+  deposit_column<NCHI, BLK>(t.args[b], l - t.first[b]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -783,9 +796,9 @@ struct MoveLds {
   static constexpr int kMom = kGlobalMom ? TC * 4 : RC * 4;  // own cells only, or tile and ring
 };
 
-// at least six wavefronts per SIMD (three 512-thread workgroups per CU): at most 80 VGPRs
-template <int NCHI, int NNU, int MODE, bool PRE, int NTH, bool MEAS = false>
-__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k_move_count(MoveArgs a) {
+// count pass over one tile (logical block lb of the box)
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH, bool MEAS>
+__device__ __forceinline__ void move_count_tile(MoveArgs a, const unsigned lb) {
   resolve_factors(a);
   using L = MoveLds<MODE, PRE>;
   __shared__ float ph[L::kPh];
@@ -795,7 +808,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
   __shared__ uint32_t pre[TC + 1];
   __shared__ uint64_t start[TC];
   __shared__ uint32_t wsum[NTH / 64];
-  const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
+  const TileGeom g = tile_of(lb, a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) mcnt[i] = 0u;
   for (int i = threadIdx.x; i < L::kMom; i += NTH) mom[i] = 0ull;
@@ -891,6 +904,20 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k
   }
 }
 
+// at least six wavefronts per SIMD (three 512-thread workgroups per CU): at most 80 VGPRs
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH, bool MEAS = false>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k_move_count(MoveArgs a) {
+  move_count_tile<NCHI, NNU, MODE, PRE, NTH, MEAS>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// every box of an ensemble in one launch (a box's workgroups: its tiles)
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
+__global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(6))) void k_move_count_boxes(BoxTable<MoveArgs> t) {
+  const unsigned l = xcd_block(blockIdx.x, gridDim.x);
+  const int b = box_of(t.first, t.nbox, l);
+  move_count_tile<NCHI, NNU, MODE, PRE, NTH, false>(t.args[b], l - t.first[b]);
+}
+
 // Eq. (nu) by the edge table: the code nu with ext[nu + h] <= u < ext[nu + h + 1] (h = (M-1)/2;
 // ext is the edge table with -inf and +inf at its ends), i.e. -h + #{edges <= u}. A bucket table
 // over t = u / (1 + |u|) gives the code at the lower end of the bucket. Every bucket holds at most
@@ -915,7 +942,7 @@ __device__ __forceinline__ int encode_nu(float u, const float* ext, const BT* bu
 }
 
 template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
-__global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
+__device__ __forceinline__ void move_scatter_tile(MoveArgs a, const unsigned lb) {
   resolve_factors(a);
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
@@ -930,7 +957,7 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   // the flag word is requested first and tested after the set-up (the last barrier): a wave that
   // returns then cannot hold up the others
   const uint32_t failed = __atomic_load_n(a.flags, __ATOMIC_RELAXED);
-  const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
+  const TileGeom g = tile_of(lb, a.nt);
   load_potential<MODE, PRE, NTH>(a, ph, gd, g);
   for (int i = threadIdx.x; i < TC * 27; i += NTH) grp[i] = 0u;
   const int nedge = 2 * a.vhalf + 2;
@@ -1002,6 +1029,18 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
   }
 }
 
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
+__global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
+  move_scatter_tile<NCHI, NNU, MODE, PRE, NTH>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int NCHI, int NNU, int MODE, bool PRE, int NTH>
+__global__ __launch_bounds__(NTH) void k_move_scatter_boxes(BoxTable<MoveArgs> t) {
+  const unsigned l = xcd_block(blockIdx.x, gridDim.x);
+  const int b = box_of(t.first, t.nbox, l);
+  move_scatter_tile<NCHI, NNU, MODE, PRE, NTH>(t.args[b], l - t.first[b]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Dense move passes (at least half as many particles as fine cells): one coarse cell per wave at
 // a time, so the cell's offset, mean velocity and scale are wave-uniform; the stayers of a cell
@@ -1009,9 +1048,8 @@ __global__ __launch_bounds__(NTH) void k_move_scatter(MoveArgs a) {
 // in storage order by a single wave, which makes the running rank per displacement exact.
 // ---------------------------------------------------------------------------------------------
 
-template <int NCHI, int NNU, bool SCATTER, bool MEAS = false>
-// two 1024-thread workgroups per CU: at most 64 VGPRs
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_move_dense(MoveArgs a) {
+template <int NCHI, int NNU, bool SCATTER, bool MEAS>
+__device__ __forceinline__ void move_dense_tile(MoveArgs a, const unsigned lb) {
   resolve_factors(a);
   using CT = chi_t<NCHI>;
   using NT = nu_t<NNU>;
@@ -1031,7 +1069,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   __shared__ float tdec_lds[NNU == 1 ? 255 : 1];
   __shared__ float edges_lds[(SCATTER && NNU == 1) ? 256 : 1];
   __shared__ int8_t bucket_lds[(SCATTER && NNU == 1) ? 1024 : 1];  // 1-byte codes fit int8
-  const TileGeom g = tile_of(xcd_block(blockIdx.x, gridDim.x), a.nt);
+  const TileGeom g = tile_of(lb, a.nt);
   // scatter: the flag word is requested first and tested after the set-up (the last barrier)
   const uint32_t failed = SCATTER ? __atomic_load_n(a.flags, __ATOMIC_RELAXED) : 0u;
   // mean velocity and decode scale of the tile's cells
@@ -1381,6 +1419,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
   }
 }
 
+// two 1024-thread workgroups per CU: at most 64 VGPRs
+template <int NCHI, int NNU, bool SCATTER, bool MEAS = false>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_move_dense(MoveArgs a) {
+  move_dense_tile<NCHI, NNU, SCATTER, MEAS>(a, xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int NCHI, int NNU, bool SCATTER>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_move_dense_boxes(BoxTable<MoveArgs> t) {
+  const unsigned l = xcd_block(blockIdx.x, gridDim.x);
+  const int b = box_of(t.first, t.nbox, l);
+  move_dense_tile<NCHI, NNU, SCATTER, false>(t.args[b], l - t.first[b]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Link: per new cell, counts from the 27 source cells in offset order (z, y, x each -1, 0, +1),
 // the slot prefix per source offset, the mean velocity and the 3-D velocity variance.
@@ -1404,11 +1455,11 @@ struct LinkArgs {
 // of a link block cannot overflow; the sum over the blocks is exact in 128 bits (k_scan_blocks)
 constexpr double kDevTermLimit = 18014398509481984.0;  // 2^54
 
-__global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) {
+__device__ __forceinline__ void link_block(const LinkArgs& a, const unsigned blk) {
   __shared__ unsigned long long sn[LINK_BLK];
   __shared__ long long sq[LINK_BLK];
   if (workgroup_step_failed(a.flags)) return;
-  const int64_t c = (int64_t)blockIdx.x * LINK_BLK + threadIdx.x;
+  const int64_t c = (int64_t)blk * LINK_BLK + threadIdx.x;
   uint32_t n = 0;
   long long q = 0;
   if (c < a.nc3) {
@@ -1470,9 +1521,16 @@ __global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    a.blk_n[blockIdx.x] = sn[0];
-    a.blk_q[blockIdx.x] = sq[0];
+    a.blk_n[blk] = sn[0];
+    a.blk_q[blk] = sq[0];
   }
+}
+
+__global__ __launch_bounds__(LINK_BLK) void k_link(LinkArgs a) { link_block(a, blockIdx.x); }
+
+__global__ __launch_bounds__(LINK_BLK) void k_link_boxes(BoxTable<LinkArgs> t) {
+  const int b = box_of(t.first, t.nbox, blockIdx.x);
+  link_block(t.args[b], blockIdx.x - t.first[b]);
 }
 
 // Nearest FP64 value (ties to even) of the unsigned 128-bit integer hi 2^64 + lo. Above 2^64 the
@@ -1489,9 +1547,26 @@ __device__ __forceinline__ double u128_to_double(unsigned long long hi, unsigned
 
 // single workgroup: exclusive scan of the per-block counts; the global dispersion, the exact sum of
 // the per-block int64 terms (each in [0, 2^62)) in 128 bits
-__global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* blk_n, const int64_t* blk_q, uint64_t* blk_off,
-                                                      int64_t nblk, uint64_t* off_end, int64_t n_expect,
-                                                      double* scal, uint32_t* flags) {
+struct ScanArgs {
+  const uint64_t* blk_n;
+  const int64_t* blk_q;
+  uint64_t* blk_off;
+  int64_t nblk;
+  uint64_t* off_end;
+  int64_t n_expect;
+  double* scal;
+  uint32_t* flags;
+};
+
+__device__ __forceinline__ void scan_blocks(const ScanArgs& a) {
+  const uint64_t* blk_n = a.blk_n;
+  const int64_t* blk_q = a.blk_q;
+  uint64_t* blk_off = a.blk_off;
+  const int64_t nblk = a.nblk;
+  uint64_t* off_end = a.off_end;
+  const int64_t n_expect = a.n_expect;
+  double* scal = a.scal;
+  uint32_t* flags = a.flags;
   __shared__ unsigned long long ps[1024];
   __shared__ unsigned long long qh[1024], ql[1024];
   if (workgroup_step_failed(flags)) return;
@@ -1539,6 +1614,13 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(uint64_t* blk_n, const int
   }
 }
 
+__global__ __launch_bounds__(1024) void k_scan_blocks(ScanArgs a) { scan_blocks(a); }
+
+// one workgroup per box
+__global__ __launch_bounds__(1024) void k_scan_blocks_boxes(const ScanArgs* __restrict__ tab) {
+  scan_blocks(tab[blockIdx.x]);
+}
+
 struct FinArgs {
   const uint32_t* cnt_n;
   const uint64_t* blk_off;
@@ -1553,15 +1635,15 @@ struct FinArgs {
   const uint32_t* flags;
 };
 
-__global__ __launch_bounds__(LINK_BLK) void k_finalize(FinArgs a) {
+__device__ __forceinline__ void finalize_block(const FinArgs& a, const unsigned blk) {
   __shared__ uint32_t pre[LINK_BLK + 1];
   __shared__ uint32_t wsum[LINK_BLK / 64];
   if (workgroup_step_failed(a.flags)) return;
-  const int64_t c = (int64_t)blockIdx.x * LINK_BLK + threadIdx.x;
+  const int64_t c = (int64_t)blk * LINK_BLK + threadIdx.x;
   const uint32_t n = (c < a.nc3) ? a.cnt_n[c] : 0u;
   block_exclusive_scan(n, pre, LINK_BLK, wsum);
   if (c >= a.nc3) return;
-  a.off_n[c] = a.blk_off[blockIdx.x] + pre[threadIdx.x];
+  a.off_n[c] = a.blk_off[blk] + pre[threadIdx.x];
   const double sg2 = a.scal[0];
   double s2c = sg2;
   if (a.sigma_mode == CUBE_SIGMA_PER_CELL) {
@@ -1571,6 +1653,13 @@ __global__ __launch_bounds__(LINK_BLK) void k_finalize(FinArgs a) {
   const double sc = sqrt(s2c) * a.sq2pi;
   a.vs_n[c] = (float)sc;
   a.vinv[c] = (float)(1.0 / sc);
+}
+
+__global__ __launch_bounds__(LINK_BLK) void k_finalize(FinArgs a) { finalize_block(a, blockIdx.x); }
+
+__global__ __launch_bounds__(LINK_BLK) void k_finalize_boxes(BoxTable<FinArgs> t) {
+  const int b = box_of(t.first, t.nbox, blockIdx.x);
+  finalize_block(t.args[b], blockIdx.x - t.first[b]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1709,11 +1798,12 @@ __global__ void k_noise(float* out, int n, int64_t pitch_f, uint64_t seed) {
     else CALL(2, 2);                                                          \
   } while (0)
 
-void launch_deposit(Sim& s, hipStream_t st) {
+// the deposit's arguments for the state of parity cur, and its grid (columns x z chunks)
+static DepArgs deposit_args(const Sim& s, int cur, dim3* grid) {
   DepArgs a;
-  a.chi = s.chi[s.cur];
-  a.cnt = s.cnt[s.cur];
-  a.off = s.off[s.cur];
+  a.chi = s.chi[cur];
+  a.cnt = s.cnt[cur];
+  a.off = s.off[cur];
   a.cap = s.capacity;
   a.mesh = s.mesh;
   a.pitch_f = (int64_t)s.mesh_plan.row_floats();
@@ -1728,7 +1818,13 @@ void launch_deposit(Sim& s, hipStream_t st) {
   nchunk = (s.nc + a.zc - 1) / a.zc;
   a.inv_mean = (double)s.nm * (double)s.nm * (double)s.nm / ((double)s.n * ldexp(1.0, 3 * (8 * s.nchi - 1)));
   a.interleave = s.deposit_variant & 1;
-  const dim3 grid((unsigned)cols, (unsigned)nchunk);
+  *grid = dim3((unsigned)cols, (unsigned)nchunk);
+  return a;
+}
+
+void launch_deposit(Sim& s, hipStream_t st) {
+  dim3 grid;
+  const DepArgs a = deposit_args(s, s.cur, &grid);
   if (s.deposit_variant & 2) {
     if (s.nchi == 1) k_deposit<1, 512><<<grid, 512, 0, st>>>(a);
     else k_deposit<2, 512><<<grid, 512, 0, st>>>(a);
@@ -1739,7 +1835,8 @@ void launch_deposit(Sim& s, hipStream_t st) {
   CUBE_HIP(hipGetLastError());
 }
 
-static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipStream_t st) {
+// arguments of the link, block-scan and finalize kernels that build state nxt
+static LinkArgs link_args(const Sim& s, int nxt, const uint32_t* cnt_direct) {
   LinkArgs l;
   l.mig = s.mig;
   l.slot = s.slot;
@@ -1753,10 +1850,14 @@ static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipS
   l.nc3 = s.nc3;
   l.cnt_direct = cnt_direct;
   l.flags = s.flags;
-  k_link<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(l);
-  CUBE_HIP(hipGetLastError());
-  k_scan_blocks<<<1, 1024, 0, st>>>(s.blk_n, s.blk_q, s.blk_off, s.nblk, s.off[nxt] + s.nc3, s.n, s.scal, s.flags);
-  CUBE_HIP(hipGetLastError());
+  return l;
+}
+
+static ScanArgs scan_args(const Sim& s, int nxt) {
+  return ScanArgs{s.blk_n, s.blk_q, s.blk_off, s.nblk, s.off[nxt] + s.nc3, s.n, s.scal, s.flags};
+}
+
+static FinArgs fin_args(const Sim& s, int nxt) {
   FinArgs f;
   f.cnt_n = s.cnt[nxt];
   f.blk_off = s.blk_off;
@@ -1769,7 +1870,15 @@ static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipS
   f.sigma_mode = s.p.sigma_mode;
   f.sq2pi = std::sqrt(2.0 / M_PI);
   f.flags = s.flags;
-  k_finalize<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(f);
+  return f;
+}
+
+static void link_scan_finalize(Sim& s, int nxt, const uint32_t* cnt_direct, hipStream_t st) {
+  k_link<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(link_args(s, nxt, cnt_direct));
+  CUBE_HIP(hipGetLastError());
+  k_scan_blocks<<<1, 1024, 0, st>>>(scan_args(s, nxt));
+  CUBE_HIP(hipGetLastError());
+  k_finalize<<<(unsigned)s.nblk, LINK_BLK, 0, st>>>(fin_args(s, nxt));
   CUBE_HIP(hipGetLastError());
 }
 
@@ -1797,16 +1906,17 @@ void launch_raise_flag(Sim& s, hipStream_t st, uint32_t f, bool dev_sched, int a
   CUBE_HIP(hipGetLastError());
 }
 
-void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
-                 hipEvent_t* evs, bool dev_sched) {
-  const int nxt = s.cur ^ 1;
+// the move passes' arguments from the state of parity cur to the other (no step maxima, no
+// initial-condition fields)
+static MoveArgs move_args(const Sim& s, int cur, float kfac, float dfac, bool dev_sched) {
+  const int nxt = cur ^ 1;
   MoveArgs a{};
-  a.chi = s.chi[s.cur];
-  a.nu = s.nu[s.cur];
-  a.cnt = s.cnt[s.cur];
-  a.off = s.off[s.cur];
-  a.vc = s.vc[s.cur];
-  a.vs = s.vs[s.cur];
+  a.chi = s.chi[cur];
+  a.nu = s.nu[cur];
+  a.cnt = s.cnt[cur];
+  a.off = s.off[cur];
+  a.vc = s.vc[cur];
+  a.vs = s.vs[cur];
   a.chi_n = s.chi[nxt];
   a.nu_n = s.nu[nxt];
   a.off_n = s.off[nxt];
@@ -1832,13 +1942,31 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
   a.flags = s.flags;
   a.kd = dev_sched ? s.sched_dev : nullptr;
   a.kstep = dev_sched ? s.step_dev : nullptr;
-  a.pid = s.pid[s.cur];
+  a.pid = s.pid[cur];
   a.pid_n = s.pid[nxt];
   a.pid_bytes = s.pid_bytes;
+  a.amax = nullptr;
+  a.turn_limit = s.turn_limit;
+  return a;
+}
+
+// which kernel each move pass of a step (mode 0) uses: the gradient tile or the per-corner gradient
+static void move_kernels(const Sim& s, int mode, bool* tile_count, bool* tile_scatter) {
+  // gradient tile per pass: variant 1 both, 2 scatter only, 3 count only, -1 when particles are at
+  // least half as many as fine cells
+  const bool dense = 2 * s.n >= (int64_t)s.nm * s.nm * s.nm;
+  const int mv = s.move_variant;
+  *tile_count = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 3));
+  *tile_scatter = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 2));
+}
+
+void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, float vfac, hipStream_t st,
+                 hipEvent_t* evs, bool dev_sched) {
+  const int nxt = s.cur ^ 1;
+  MoveArgs a = move_args(s, s.cur, kfac, dfac, dev_sched);
   // step maxima for adaptive time steps (a small fill kernel clears them: no memset node in
   // captured graphs, although adaptive simulations are never captured)
   a.amax = (mode == 0 && s.amax) ? s.amax : nullptr;
-  a.turn_limit = s.turn_limit;
   if (a.amax) {
     k_clear_u32<<<1, 64, 0, st>>>(s.amax, 2);
     CUBE_HIP(hipGetLastError());
@@ -1854,12 +1982,8 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
     a.lunit = (float)(2.0 / (double)a.q);
   }
   const unsigned grid = (unsigned)((int64_t)a.nt * a.nt * a.nt);
-  // precomputed gradient tile when particles are at least half as many as fine cells
-  // gradient tile per pass: variant 1 both, 2 scatter only, 3 count only, -1 by density
-  const bool dense = 2 * s.n >= (int64_t)s.nm * s.nm * s.nm;
-  const int mv = s.move_variant;
-  const bool tile_count = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 3));
-  const bool tile_scatter = mode == 0 && (mv < 0 ? dense : (mv == 1 || mv == 2));
+  bool tile_count, tile_scatter;
+  move_kernels(s, mode, &tile_count, &tile_scatter);
 #define CUBE_COUNT(X, V)                                                                        \
   do {                                                                                          \
     if (tile_count && a.amax) k_move_dense<X, V, false, true><<<grid, 1024, 0, st>>>(a);         \
@@ -1888,6 +2012,169 @@ void launch_move(Sim& s, int mode, float kfac, float dfac, float* const* psi, fl
 #undef CUBE_COUNT
 #undef CUBE_SCATTER
   s.cur = nxt;
+}
+
+// ---- ensemble steps: one launch per stage over every box ---------------------------------------
+size_t EnsembleStep::put(const void* p, size_t bytes) {
+  const size_t off = (staged.size() + 255) & ~(size_t)255;
+  staged.resize(off + bytes);
+  if (bytes) std::memcpy(staged.data() + off, p, bytes);
+  return off;
+}
+
+void EnsembleStep::upload() {
+  if (dbase || staged.empty()) return;
+  CUBE_HIP(hipMalloc(&dbase, staged.size()));
+  CUBE_HIP(hipMemcpy(dbase, staged.data(), staged.size(), hipMemcpyHostToDevice));
+}
+
+EnsembleStep::~EnsembleStep() {
+  if (dbase) (void)hipFree(dbase);
+}
+
+namespace {
+
+// a staged per-box argument table with the first workgroup of each box
+struct StagedBoxes {
+  size_t args, first;
+  int nbox;
+  unsigned blocks;  // workgroups of the launch
+};
+
+template <class A>
+StagedBoxes stage_boxes(EnsembleStep& es, const std::vector<A>& args, const std::vector<uint32_t>& per_box,
+                        int threads) {
+  std::vector<uint32_t> first(1, 0u);
+  uint64_t t = 0;
+  for (uint32_t b : per_box) {
+    t += b;
+    first.push_back((uint32_t)t);
+  }
+  // a dispatch holds fewer than 2^32 work-items
+  if (t * (uint64_t)threads >= (1ull << 32)) throw Error{CUBE_E_INVALID, "ensemble too large for one launch per stage"};
+  return StagedBoxes{es.put(args), es.put(first), (int)args.size(), (unsigned)t};
+}
+
+template <class A>
+BoxTable<A> table_of(const EnsembleStep* e, const StagedBoxes& g) {
+  return BoxTable<A>{e->at<A>(g.args), e->at<uint32_t>(g.first), g.nbox};
+}
+
+struct EndArgs {
+  uint32_t* flags;
+  int* step;
+};
+
+// k_step_end of every box (device step counters), one thread per box
+__global__ void k_step_end_boxes(const EndArgs* __restrict__ tab, int nbox) {
+  const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (b >= nbox) return;
+  uint32_t* flags = tab[b].flags;
+  int* step = tab[b].step;
+  const uint32_t code = (uint32_t)step[0] + 2u;
+  step[0] += 1;
+  if (flags[0] != 0u && flags[1] == 0u) flags[1] = code;
+}
+
+}  // namespace
+
+void ensemble_deposit(EnsembleStep& es, const std::vector<Sim*>& boxes) {
+  const EnsembleStep* e = &es;
+  for (int nchi = 1; nchi <= 2; ++nchi)
+    for (int blk : {256, 512}) {
+      std::vector<DepArgs> args;
+      std::vector<uint32_t> per;
+      for (Sim* s : boxes) {
+        if (s->nchi != nchi || ((s->deposit_variant & 2) ? 512 : 256) != blk) continue;
+        dim3 g;
+        args.push_back(deposit_args(*s, s->cur, &g));
+        per.push_back(g.x * g.y);
+      }
+      if (args.empty()) continue;
+      const StagedBoxes g = stage_boxes(es, args, per, blk);
+      es.launches.push_back([e, g, nchi, blk](hipStream_t st) {
+        const BoxTable<DepArgs> t = table_of<DepArgs>(e, g);
+        if (nchi == 1 && blk == 512) k_deposit_boxes<1, 512><<<g.blocks, 512, 0, st>>>(t);
+        else if (nchi == 1) k_deposit_boxes<1, 256><<<g.blocks, 256, 0, st>>>(t);
+        else if (blk == 512) k_deposit_boxes<2, 512><<<g.blocks, 512, 0, st>>>(t);
+        else k_deposit_boxes<2, 256><<<g.blocks, 256, 0, st>>>(t);
+        CUBE_HIP(hipGetLastError());
+      });
+    }
+}
+
+void ensemble_move(EnsembleStep& es, const std::vector<Sim*>& boxes) {
+  const EnsembleStep* e = &es;
+  // one pass over the boxes grouped by codec and kernel (gradient tile or per-corner gradient)
+  auto pass = [&](bool scatter) {
+    for (int xv = 0; xv < 4; ++xv)
+      for (int tile = 0; tile <= 1; ++tile) {
+        const int nchi = 1 + (xv >> 1), nnu = 1 + (xv & 1);
+        std::vector<MoveArgs> args;
+        std::vector<uint32_t> per;
+        for (Sim* s : boxes) {
+          bool tc, ts;
+          move_kernels(*s, 0, &tc, &ts);
+          if (s->nchi != nchi || s->nnu != nnu || (scatter ? ts : tc) != (tile != 0)) continue;
+          args.push_back(move_args(*s, s->cur, 0.0f, 0.0f, true));
+          const int64_t nt = s->nc / T;
+          per.push_back((uint32_t)(nt * nt * nt));
+        }
+        if (args.empty()) continue;
+        const StagedBoxes g = stage_boxes(es, args, per, tile ? 1024 : 512);
+        es.launches.push_back([e, g, nchi, nnu, tile, scatter](hipStream_t st) {
+          const BoxTable<MoveArgs> t = table_of<MoveArgs>(e, g);
+#define CUBE_PASS(X, V)                                                                                 \
+  do {                                                                                                  \
+    if (tile && scatter) k_move_dense_boxes<X, V, true><<<g.blocks, 1024, 0, st>>>(t);                   \
+    else if (tile) k_move_dense_boxes<X, V, false><<<g.blocks, 1024, 0, st>>>(t);                        \
+    else if (scatter) k_move_scatter_boxes<X, V, 0, false, 512><<<g.blocks, 512, 0, st>>>(t);            \
+    else k_move_count_boxes<X, V, 0, false, 512><<<g.blocks, 512, 0, st>>>(t);                           \
+  } while (0)
+          CUBE_XV_DISPATCH(nchi, nnu, CUBE_PASS);
+#undef CUBE_PASS
+          CUBE_HIP(hipGetLastError());
+        });
+      }
+  };
+  pass(false);
+  // link, block scan and finalize of every box
+  std::vector<LinkArgs> la;
+  std::vector<ScanArgs> sa;
+  std::vector<FinArgs> fa;
+  std::vector<uint32_t> per;
+  for (Sim* s : boxes) {
+    const int nxt = s->cur ^ 1;
+    la.push_back(link_args(*s, nxt, nullptr));
+    sa.push_back(scan_args(*s, nxt));
+    fa.push_back(fin_args(*s, nxt));
+    per.push_back((uint32_t)s->nblk);
+  }
+  const StagedBoxes gl = stage_boxes(es, la, per, LINK_BLK);
+  const StagedBoxes gf = stage_boxes(es, fa, per, LINK_BLK);
+  const size_t os = es.put(sa);
+  const unsigned nbox = (unsigned)boxes.size();
+  es.launches.push_back([e, gl, gf, os, nbox](hipStream_t st) {
+    k_link_boxes<<<gl.blocks, LINK_BLK, 0, st>>>(table_of<LinkArgs>(e, gl));
+    CUBE_HIP(hipGetLastError());
+    k_scan_blocks_boxes<<<nbox, 1024, 0, st>>>(e->at<ScanArgs>(os));
+    CUBE_HIP(hipGetLastError());
+    k_finalize_boxes<<<gf.blocks, LINK_BLK, 0, st>>>(table_of<FinArgs>(e, gf));
+    CUBE_HIP(hipGetLastError());
+  });
+  pass(true);
+}
+
+void ensemble_step_end(EnsembleStep& es, const std::vector<Sim*>& boxes) {
+  std::vector<EndArgs> t;
+  for (Sim* s : boxes) t.push_back(EndArgs{s->flags, s->step_dev});
+  const size_t ot = es.put(t);
+  const int nbox = (int)boxes.size();
+  const EnsembleStep* e = &es;
+  es.launches.push_back([e, ot, nbox](hipStream_t st) {
+    k_step_end_boxes<<<(unsigned)((nbox + 63) / 64), 64, 0, st>>>(e->at<EndArgs>(ot), nbox);
+    CUBE_HIP(hipGetLastError());
+  });
 }
 
 void launch_load(Sim& s, const double* dx, const float* /*unused*/, int64_t n, hipStream_t st) {

@@ -73,6 +73,69 @@ def test_batch_stream_mode_equals_alone(lib):
         assert_same(got[i], run_alone(lib, cfg, 5), f"box {i}")
 
 
+def test_ensemble_launches_equal_alone(lib):
+    """Mode 2: every stage one launch over all boxes (three mesh sizes, a 2-byte position box)."""
+    cfgs = small_ensemble()
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        b.set_mode(b.ENSEMBLE)
+        b.step(3)
+        b.step(4)  # both state parities
+        b.set_mode(b.GRAPH)  # the modes can be mixed
+        b.step(1)
+        b.set_mode(b.ENSEMBLE)
+        b.step(2)
+        got = [box.get_state() for box in b.boxes]
+        assert all(box.steps_done == 10 for box in b.boxes)
+    for i, cfg in enumerate(cfgs):
+        assert_same(got[i], run_alone(lib, cfg, 10), f"box {i}")
+
+
+# per-box kernel variants: boxes of one stage then take different kernels (one launch each)
+ENSEMBLE_VARIANTS = [dict(move_variant=1, deposit_variant=0), dict(move_variant=2, fft_z_layout=1, deposit_variant=1),
+                     dict(move_variant=3, deposit_variant=2, fft_z_order=1), dict(move_variant=0, fft_col_width=8)]
+
+
+def test_ensemble_launches_with_mixed_variants(lib):
+    cfgs = small_ensemble()
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        for box, v in zip(b.boxes, ENSEMBLE_VARIANTS):
+            box.set_variant(**v)
+        b.boxes[2].enable_pids(4)
+        b.set_mode(b.ENSEMBLE)
+        b.step(5)
+        got = [box.get_state() for box in b.boxes]
+        pids = b.boxes[2].get_pids()
+    for i, cfg in enumerate(cfgs):
+        with lib.Sim(**cfg) as s:
+            s.init_ic()
+            s.set_variant(**ENSEMBLE_VARIANTS[i])
+            if i == 2:
+                s.enable_pids(4)
+            s.step(5)
+            assert_same(got[i], s.get_state(), f"box {i}")
+            if i == 2:
+                assert np.array_equal(pids, s.get_pids())
+
+
+def test_ensemble_launches_need_single_level_solves(lib):
+    cfgs = [small_ensemble()[i] for i in (0, 3)]  # 16^3 coarse meshes: the two-level force is available
+    with lib.Batch(cfgs) as b:
+        b.init_ic()
+        b.boxes[1].set_two_level(6.0)
+        with pytest.raises(lib.CubeError) as e:
+            b.set_mode(b.ENSEMBLE)
+        assert e.value.code == -1 and "box 1" in str(e.value)  # CUBE_E_INVALID
+        b.boxes[1].set_two_level(0.0)
+        b.set_mode(b.ENSEMBLE)
+        b.boxes[0].set_two_level(6.0)  # switched on after the mode: the step refuses
+        with pytest.raises(lib.CubeError) as e:
+            b.step(1)
+        assert e.value.code == -1
+        assert [box.steps_done for box in b.boxes] == [0, 0]
+
+
 def test_batch_autotune_keeps_results(lib):
     cfgs = small_ensemble()[:3]
     with lib.Batch(cfgs) as b:
@@ -134,7 +197,7 @@ def test_batch_refuses_boxes_out_of_step(lib):
         assert "same step" in str(e.value)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_failed_box_stops_at_its_step(lib, mode):
     """A box whose step fails (a CFL error raised from the host before the move of step 2) stays at
     the state before that step; the other boxes complete their steps."""
