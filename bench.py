@@ -157,57 +157,66 @@ def cpu_baseline(steps: dict):
     }
 
 
-def bench_ensemble(args) -> dict:
-    """The 64-box ensemble (synth.ensemble): all boxes stepped together with cube_batch_step
-    (variants autotuned per box shape) in each launch mode -- kernels on per-box streams, one graph
-    of per-box branches, one graph of ensemble launches (one launch per stage over all boxes) --
-    each mode continuing the run for the same number of steps, against the same boxes stepped one
-    after another with cube_step over the steps the last mode ran; box 0's state after them is
-    compared bit for bit."""
+def time_ensemble(cfgs, steps: int, warmup: int, label: str) -> dict:
+    """cfgs stepped together with cube_batch_step (variants autotuned per box shape) in each launch
+    mode -- kernels on per-box streams, one graph of per-box branches, one graph of ensemble
+    launches (one launch per stage over all boxes) -- each mode continuing the run for `steps`
+    steps, against the same boxes stepped one after another with cube_step over the steps the last
+    mode ran; box 0's state after them is compared bit for bit."""
     import numpy as np
     import torch
     from paper_1712_06121_amd import Batch, Sim
 
-    cfgs = synth.ensemble(n_steps=50)
-    total = sum(c["np_side"] ** 3 for c in cfgs)
-    print(f"[bench] ensemble: {len(cfgs)} boxes, {total / 1e6:.1f} M particles", file=sys.stderr, flush=True)
     b = Batch(cfgs)
     b.init_ic()
     b.autotune()
-    b.step(args.warmup)
+    b.step(warmup)
     torch.cuda.synchronize()
-    # both launch modes, each over the same number of steps (the second continues the run)
     t_mode = {}
     modes = ((Batch.STREAMS, "streams"), (Batch.GRAPH, "graph"), (Batch.ENSEMBLE, "ensemble"))
     for mode, name in modes:
         b.set_mode(mode)
         t0 = time.perf_counter()
-        b.step(args.steps)
+        b.step(steps)
         torch.cuda.synchronize()
         t_mode[name] = time.perf_counter() - t0
-    best_mode = min(t_mode, key=t_mode.get)
-    t_batch = t_mode[best_mode]
     ref0 = b.boxes[0].get_state()
     variants = sorted({(c["np_side"], tuple(box.variant.values())) for c, box in zip(cfgs, b.boxes)})
     dev_bytes = sum(box.device_bytes for box in b.boxes)
     b.close()
-    print(f"[bench] batch: {args.steps} steps in {t_mode}, variants {variants}", file=sys.stderr, flush=True)
+    print(f"[bench] {label} batch: {steps} steps in {t_mode}, variants {variants}", file=sys.stderr, flush=True)
     t_seq = 0.0
     same0 = None
     for i, c in enumerate(cfgs):
         with Sim(**c) as s:
             s.init_ic()
-            # the steps the last mode timed; box 0 is compared with the batch at the same step
-            s.step(args.warmup + (len(modes) - 1) * args.steps)
+            s.step(warmup + (len(modes) - 1) * steps)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.step(args.steps)
+            s.step(steps)
             torch.cuda.synchronize()
             t_seq += time.perf_counter() - t0
             if i == 0:
                 st = s.get_state()
                 same0 = all(np.array_equal(st[k], ref0[k]) for k in ("cnt", "chi", "nu", "vc", "vs"))
-    print(f"[bench] sequential: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    print(f"[bench] {label} sequential: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    best = min(t_mode, key=t_mode.get)
+    return dict(t_mode=t_mode, t_seq=t_seq, best=best, same0=same0, variants=variants, dev_bytes=dev_bytes)
+
+
+def bench_ensemble(args) -> dict:
+    """The 64-box ensemble (synth.ensemble), timed in every batch launch mode against sequential
+    cube_step (time_ensemble); beside it, 64 boxes of 32^3 particles (synth.ensemble_small), whose
+    kernels alone leave most of the GPU idle."""
+    cfgs = synth.ensemble(n_steps=50)
+    total = sum(c["np_side"] ** 3 for c in cfgs)
+    print(f"[bench] ensemble: {len(cfgs)} boxes, {total / 1e6:.1f} M particles", file=sys.stderr, flush=True)
+    r = time_ensemble(cfgs, args.steps, args.warmup, "c4")
+    small = synth.ensemble_small(n_steps=100)
+    small_total = sum(c["np_side"] ** 3 for c in small)
+    rs = time_ensemble(small, 4 * args.steps, args.warmup, "small")
+    t_mode, t_seq, best_mode, same0, dev_bytes = r["t_mode"], r["t_seq"], r["best"], r["same0"], r["dev_bytes"]
+    t_batch = t_mode[best_mode]
     step_bytes = sum(sum(algorithmic_bytes(c).values()) for c in cfgs)
     k_step = t_batch / args.steps
     return {
@@ -233,6 +242,12 @@ def bench_ensemble(args) -> dict:
         "sequential": {"value": total * args.steps / t_seq, "seconds": t_seq},
         "speedup_vs_sequential": t_seq / t_batch,
         "speedup_vs_sequential_by_mode": {k: t_seq / v for k, v in t_mode.items()},
+        "small_boxes": {"workload": f"{len(small)} boxes of 32^3 particles (mesh 64^3), x1v1",
+                        "steps": 4 * args.steps, "particle_steps_per_s_by_mode":
+                            {k: small_total * 4 * args.steps / v for k, v in rs["t_mode"].items()},
+                        "sequential_particle_steps_per_s": small_total * 4 * args.steps / rs["t_seq"],
+                        "speedup_vs_sequential_by_mode": {k: rs["t_seq"] / v for k, v in rs["t_mode"].items()},
+                        "box0_bit_identical": rs["same0"]},
         "batch_seconds_by_mode": t_mode,
         "batch_mode": best_mode,
         "box0_bit_identical": same0,

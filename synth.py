@@ -50,6 +50,17 @@ def ensemble(seed: int = 4, nbox: int = 64, n_steps: int = 50) -> list[dict]:
     return out
 
 
+def ensemble_small(seed: int = 6, nbox: int = 64, side: int = 32, n_steps: int = 50) -> list[dict]:
+    """Ensemble of equal small boxes (side^3 particles, mesh twice that per side, coarse cells a
+    quarter of the mesh, 1.5625 Mpc/h per particle spacing), the same cosmology draws as ensemble:
+    each box's kernels alone occupy a fraction of the GPU."""
+    g = rng(seed)
+    return [dict(np_side=side, nm_side=2 * side, nc_side=side // 2, box=1.5625 * side, x_bytes=1, v_bytes=1,
+                 omega_m=0.3, omega_l=0.7, h=0.7, sigma8=float(g.uniform(0.7, 0.9)), n_s=float(g.uniform(0.9, 1.0)),
+                 a_init=0.02, a_final=1.0, n_steps=n_steps, spacing=1, seed=2000 + 17 * seed + i)
+            for i in range(nbox)]
+
+
 def serving_jobs(seed: int = 5, n: int = 2000, rate: float = 20.0, n_steps: int = 50) -> list[dict]:
     """A Poisson stream of simulation requests: exponential gaps of mean 1/rate seconds; particles
     per side 64, 128 or 256 with probabilities 0.5, 0.35, 0.15; mesh twice and coarse cells half the
