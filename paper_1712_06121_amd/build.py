@@ -18,12 +18,14 @@ ARCH = os.environ.get("CUBE_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument"]
-# Codec, deposit and move arithmetic must follow one IEEE sequence: no FMA contraction. The
-# particle kernels' atomics are either issued by one lane or go to per-lane addresses, so the
-# compiler's wavefront-combining of atomics only adds instructions there.
+# No FMA contraction anywhere: the codec, deposit and move arithmetic follows one IEEE sequence,
+# and the fused multiply-adds the kernels use are written out, so that every instantiation of a
+# kernel (FFT size, column width, layout) rounds the same operations the same way. The particle
+# kernels' atomics are either issued by one lane or go to per-lane addresses, so the compiler's
+# wavefront-combining of atomics only adds instructions there.
 PER_FILE = {
     "particles.hip": ["-ffp-contract=off", "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
-    "fft.hip": ["-ffp-contract=fast"],
+    "fft.hip": ["-ffp-contract=off"],
     "api.cpp": ["-ffp-contract=off"],
     "cosmo.cpp": ["-ffp-contract=off"],
     "batch.cpp": ["-ffp-contract=off"],

@@ -30,8 +30,11 @@ constexpr int next_radix(int rem) {
 
 __device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// The file is compiled without floating-point contraction, and the fused multiply-adds are
+// written out: every instantiation (transform size, column width, layout) then rounds the same
+// operations the same way, so the variants of a pass give bit-identical results.
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
@@ -84,11 +87,10 @@ __device__ __forceinline__ void dft3(float2* v) {
   const float h = 0.86602540378443864676f * (float)DIR;  // DIR * sqrt(3) / 2
   const float2 t1 = v[1] + v[2];
   const float2 d = v[1] - v[2];
-  const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-  const float2 iu = make_float2(-h * d.y, h * d.x);
+  const float2 t2 = make_float2(__builtin_fmaf(-0.5f, t1.x, v[0].x), __builtin_fmaf(-0.5f, t1.y, v[0].y));
   v[0] = v[0] + t1;
-  v[1] = t2 + iu;
-  v[2] = t2 - iu;
+  v[1] = make_float2(__builtin_fmaf(-h, d.y, t2.x), __builtin_fmaf(h, d.x, t2.y));
+  v[2] = make_float2(__builtin_fmaf(h, d.y, t2.x), __builtin_fmaf(-h, d.x, t2.y));
 }
 template <>
 __device__ __forceinline__ void dft<3, -1>(float2* v) { dft3<-1>(v); }
@@ -114,19 +116,21 @@ __device__ __forceinline__ void dft8(float2* v) {
   float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
   dft4<DIR>(e0, e1, e2, e3);
   dft4<DIR>(o0, o1, o2, o3);
+  // o1 exp(DIR i pi / 4) = c u1 and o3 exp(DIR 3 i pi / 4) = c u3 (d = +-1: u1, u3 are exact), the
+  // products by c fused into the butterfly's additions
   const float c = 0.70710678118654752440f;
   const float d = (float)DIR;
-  float2 w1 = make_float2(c * (o1.x - d * o1.y), c * (o1.y + d * o1.x));
-  float2 w2 = mul_pi2<DIR>(o2);
-  float2 w3 = make_float2(-c * (o3.x + d * o3.y), c * (d * o3.x - o3.y));
+  const float2 u1 = make_float2(o1.x - d * o1.y, o1.y + d * o1.x);
+  const float2 u3 = make_float2(-(o3.x + d * o3.y), d * o3.x - o3.y);
+  const float2 w2 = mul_pi2<DIR>(o2);
   v[0] = e0 + o0;
   v[4] = e0 - o0;
-  v[1] = e1 + w1;
-  v[5] = e1 - w1;
+  v[1] = make_float2(__builtin_fmaf(c, u1.x, e1.x), __builtin_fmaf(c, u1.y, e1.y));
+  v[5] = make_float2(__builtin_fmaf(-c, u1.x, e1.x), __builtin_fmaf(-c, u1.y, e1.y));
   v[2] = e2 + w2;
   v[6] = e2 - w2;
-  v[3] = e3 + w3;
-  v[7] = e3 - w3;
+  v[3] = make_float2(__builtin_fmaf(c, u3.x, e3.x), __builtin_fmaf(c, u3.y, e3.y));
+  v[7] = make_float2(__builtin_fmaf(-c, u3.x, e3.x), __builtin_fmaf(-c, u3.y, e3.y));
 }
 template <>
 __device__ __forceinline__ void dft<8, -1>(float2* v) { dft8<-1>(v); }
@@ -443,7 +447,7 @@ __device__ __forceinline__ void fft_col_block(const float2* __restrict__ src, fl
           const float2 bt = cmul(cmul(c.inv_b[fz + c.half], c.inv_b[fy + c.half]), c.inv_b[xc + c.half]);
           const float2 u = cmul(dc, bt);
           const float sc = s * c.scale;
-          r = make_float2(r.x + sc * u.x, r.y + sc * u.y);
+          r = make_float2(__builtin_fmaf(sc, u.x, r.x), __builtin_fmaf(sc, u.y, r.y));
         }
         lds[i] = make_float2(r.x * g, r.y * g);
       }
@@ -485,7 +489,7 @@ __device__ __forceinline__ void fft_col_block(const float2* __restrict__ src, fl
       if (m < 1 || m > a.half) continue;
       const double w = (xc == 0 || xc == a.half) ? 1.0 : 2.0;
       const float2 v = lds[i];
-      const double p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      const double p = __builtin_fma((double)v.x, (double)v.x, (double)v.y * (double)v.y);
       atomicAdd(&acc[m], w * p);
       atomicAdd(&acc[NB + m], w * sqrt((double)n2));
       atomicAdd(&acc[2 * NB + m], w);
@@ -792,9 +796,9 @@ __global__ __launch_bounds__(1024) void k_cross_shells(CrossArgs c) {
     const float2 u = c.a[((int64_t)za * c.na + ya) * c.pa + fx];
     const float2 v = c.b[((int64_t)zb * c.nb + yb) * c.pb + fx];
     const double w = (fx == 0 || fx == half) ? 1.0 : 2.0;
-    atomicAdd(&sacc[m], w * ((double)u.x * v.x + (double)u.y * v.y));
-    atomicAdd(&sacc[nsh + m], w * ((double)u.x * u.x + (double)u.y * u.y));
-    atomicAdd(&sacc[2 * nsh + m], w * ((double)v.x * v.x + (double)v.y * v.y));
+    atomicAdd(&sacc[m], w * __builtin_fma((double)u.x, (double)v.x, (double)u.y * v.y));
+    atomicAdd(&sacc[nsh + m], w * __builtin_fma((double)u.x, (double)u.x, (double)u.y * u.y));
+    atomicAdd(&sacc[2 * nsh + m], w * __builtin_fma((double)v.x, (double)v.x, (double)v.y * v.y));
     atomicAdd(&sacc[3 * nsh + m], w * sqrt((double)n2));
     atomicAdd(&sacc[4 * nsh + m], w);
   }
@@ -905,7 +909,7 @@ __global__ __launch_bounds__(RBLK) void k_restrict(const float* __restrict__ mes
       const int y = i / RT, c = i - (i / RT) * RT;
       float acc = 0.0f;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) acc += w[b] * plane[y * RF + 4 * c + b];
+      for (int b = 0; b < 8; ++b) acc = __builtin_fmaf(w[b], plane[y * RF + 4 * c + b], acc);
       xr[i] = acc;
     }
     __syncthreads();
@@ -913,7 +917,7 @@ __global__ __launch_bounds__(RBLK) void k_restrict(const float* __restrict__ mes
       const int cy = threadIdx.x / RT, cx = threadIdx.x % RT;
       float acc = 0.0f;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) acc += w[b] * xr[(4 * cy + b) * RT + cx];
+      for (int b = 0; b < 8; ++b) acc = __builtin_fmaf(w[b], xr[(4 * cy + b) * RT + cx], acc);
       ring[(fz & 7) * RT * RT + threadIdx.x] = acc;
     }
     __syncthreads();
@@ -922,7 +926,7 @@ __global__ __launch_bounds__(RBLK) void k_restrict(const float* __restrict__ mes
       const int c = (fz - 5) / 4;
       float acc = 0.0f;
 #pragma unroll
-      for (int b = 0; b < 8; ++b) acc += w[b] * ring[((4 * c - 2 + b) & 7) * RT * RT + threadIdx.x];
+      for (int b = 0; b < 8; ++b) acc = __builtin_fmaf(w[b], ring[((4 * c - 2 + b) & 7) * RT * RT + threadIdx.x], acc);
       out[((int64_t)c * nc + cy0 + threadIdx.x / RT) * opitch_f + cx0 + threadIdx.x % RT] = acc;
     }
 #pragma unroll
