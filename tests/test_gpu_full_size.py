@@ -242,3 +242,34 @@ def test_full_size_sampled_cells_bit_exact(lib):
         assert np.array_equal(st1.vc[:, 0], new.vc[:, ctr]) and st1.vs[0] == new.vs[ctr], f"statistics of cell {c}"
         print(f"cell {c}: {m} particles from offset {off1[0]} bit-exact (density of its 64 fine cells too)")
     assert max(int(o[0]) for _, o in subs1) > 2**32
+
+
+def test_full_size_deposit_variants_agree(lib):
+    """At 2048^3 after a few steps, every deposit variant (both particle orders, both workgroup
+    sizes) gives the same FP32 mesh bit for bit (compared through per-row sums of the values' bit
+    patterns, plane block by plane block, so that no second mesh is held)."""
+    import torch
+    torch.cuda.empty_cache()
+    cfg = synth.WORKLOADS[NAME]
+    need = lib.footprint(**cfg) + (8 << 30)
+    free, _ = torch.cuda.mem_get_info()
+    if free < need:
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} GiB free")
+    nm = cfg["nm_side"]
+    sums = {}
+    with lib.Sim(**cfg) as sim:
+        sim.init_ic()
+        sim.step(3)
+        for v in (3, 0, 1, 2):
+            sim.set_variant(deposit_variant=v)
+            sim.stage_deposit()
+            mesh = sim.get_mesh(device=True)
+            rows = []
+            for z in range(0, nm, 64):
+                rows.append(mesh[z:z + 64].view(torch.int32).to(torch.int64).sum(dim=2))
+            sums[v] = torch.cat(rows)
+            del mesh, rows
+            torch.cuda.empty_cache()
+    ref = sums[3]
+    for v, s in sums.items():
+        assert torch.equal(s, ref), f"deposit variant {v}: {int((s != ref).sum())} rows differ"
