@@ -29,7 +29,7 @@ import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 # 32-bit vector ALU operations per second without packed math: 256 CUs x 4 SIMDs x 16 lanes x
-# 2.4 GHz, an FMA counting as two (packed FP32, which would double it, is disabled in the build)
+# 2.4 GHz, an FMA counting as two (packed FP32, which would double it, is disabled in the compile flags)
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 # arithmetic operations per particle that the method itself needs in each move pass (decode,
 # CIC weights, gradient interpolation, kick, drift, new cell, moments / encode)
@@ -356,8 +356,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (one box per GPU; "
-              "the sharded design is described in DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path (independent boxes "
+              "would be placed whole on GPUs; one box would be cut into z-slabs). Use --gpus 1.", file=sys.stderr)
         return 2
 
     import torch

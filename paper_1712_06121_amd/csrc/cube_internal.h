@@ -173,7 +173,7 @@ struct Sim {
   int steps_done = 0;
   bool half_drift_done = false;
   int move_variant = 0;     // move passes: -1 by particle density, 0 per-corner gradient, 1 gradient tile
-  int deposit_variant = 3;  // bit 0: interleaved particle order, bit 1: 512-thread workgroups, bit 2: grouped cells
+  int deposit_variant = 3;  // bit 0: interleaved particle order, bit 1: 512-thread workgroups
   std::string autotune_report;  // per-variant times of the last cube_autotune
   double a_now = 0.0;
   bool have_particles = false;

@@ -46,7 +46,7 @@ def test_fine_part_is_short_range():
     r_s: at r = 4 r_s it is below 10% of the whole, and from 6 r_s on below 3%. (The continuous split
     alone would leave erfc(u) + 2u exp(-u^2)/sqrt(pi) with u = r/(2 r_s), 4e-4 at 6 r_s; the rest is
     the lattice kernel 1/k^2's tail, which the single-level force has too. A tile-by-tile solve with
-    a buffer of 6 r_s would drop it; this build solves the fine part over the whole mesh.)"""
+    a buffer of 6 r_s would drop it; the library solves the fine part over the whole mesh.)"""
     nm, nc, r_s = 64, 16, 4.0
     delta = np.zeros((nm, nm, nm))
     delta[0, 0, 0] = nm**3
