@@ -1376,7 +1376,7 @@ __device__ __forceinline__ void move_dense_tile(MoveArgs a, const unsigned lb) {
           uint32_t spins = 0;
           while (__hip_atomic_load(&turn[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != chunk &&
                  __hip_atomic_load(&turn[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u) {
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(0);
             if (++spins >= a.turn_limit) {
               if (lane == 0) {
                 __hip_atomic_store(&turn[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1559,42 +1559,37 @@ struct ScanArgs {
 };
 
 __device__ __forceinline__ void scan_blocks(const ScanArgs& a) {
-  const uint64_t* blk_n = a.blk_n;
-  const int64_t* blk_q = a.blk_q;
-  uint64_t* blk_off = a.blk_off;
-  const int64_t nblk = a.nblk;
-  uint64_t* off_end = a.off_end;
-  const int64_t n_expect = a.n_expect;
-  double* scal = a.scal;
-  uint32_t* flags = a.flags;
-  __shared__ unsigned long long ps[1024];
   __shared__ unsigned long long qh[1024], ql[1024];
-  if (workgroup_step_failed(flags)) return;
-  const int tid = threadIdx.x;
-  const int64_t per = (nblk + 1023) / 1024;
-  const int64_t b0 = tid * per, b1 = (b0 + per < nblk) ? b0 + per : nblk;
+  __shared__ unsigned long long wtot[16];
+  if (workgroup_step_failed(a.flags)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // each wavefront takes one contiguous range of the blocks, its lanes consecutive entries (the
+  // loads of a wavefront coalesce); first its total count and the lanes' 128-bit dispersion sums
+  const int64_t per = (a.nblk + 15) / 16;
+  const int64_t b0 = min((int64_t)wave * per, a.nblk), b1 = min(b0 + per, a.nblk);
   unsigned long long s = 0, hi = 0, lo = 0;
-  for (int64_t b = b0; b < b1; ++b) {
-    s += blk_n[b];
-    const unsigned long long q = (unsigned long long)blk_q[b];
+#pragma unroll 4
+  for (int64_t b = b0 + lane; b < b1; b += 64) {
+    s += a.blk_n[b];
+    const unsigned long long q = (unsigned long long)a.blk_q[b];
     lo += q;
     hi += lo < q ? 1ull : 0ull;
   }
-  ps[tid] = s;
+  const unsigned long long ws = wave_sum_u64(s);
+  if (lane == 0) wtot[wave] = ws;
   qh[tid] = hi;
   ql[tid] = lo;
   __syncthreads();
-  // inclusive scan (Hillis-Steele) of ps; tree sum of the 128-bit dispersion terms
-  for (int o = 1; o < 1024; o <<= 1) {
-    unsigned long long add = (tid >= o) ? ps[tid - o] : 0ull;
-    __syncthreads();
-    ps[tid] += add;
-    __syncthreads();
-  }
-  unsigned long long run = ps[tid] - s;
-  for (int64_t b = b0; b < b1; ++b) {
-    blk_off[b] = run;
-    run += blk_n[b];
+  // then the exclusive prefix of its range, 64 entries at a time, from the totals of the
+  // wavefronts before it
+  unsigned long long base = 0;
+  for (int w = 0; w < wave; ++w) base += wtot[w];
+  for (int64_t c = b0; c < b1; c += 64) {
+    const int64_t b = c + lane;
+    const unsigned long long n = b < b1 ? a.blk_n[b] : 0ull;
+    const unsigned long long inc = wave_scan_u64(n);
+    if (b < b1) a.blk_off[b] = base + inc - n;
+    base += read_lane_u64(inc, 63);
   }
   for (int o = 512; o > 0; o >>= 1) {
     if (tid < o) {
@@ -1605,12 +1600,13 @@ __device__ __forceinline__ void scan_blocks(const ScanArgs& a) {
     __syncthreads();
   }
   if (tid == 0) {
-    const unsigned long long total = ps[1023];
-    *off_end = total;
-    if ((int64_t)total != n_expect) atomicOr(flags, FLAG_COUNT);
-    double sg2 = u128_to_double(qh[0], ql[0]) / ((3.0 * (double)n_expect) * 1048576.0);
+    unsigned long long total = 0;
+    for (int w = 0; w < 16; ++w) total += wtot[w];
+    *a.off_end = total;
+    if ((int64_t)total != a.n_expect) atomicOr(a.flags, FLAG_COUNT);
+    double sg2 = u128_to_double(qh[0], ql[0]) / ((3.0 * (double)a.n_expect) * 1048576.0);
     if (!(sg2 > 0.0)) sg2 = 8.673617379884035e-19;  // 2^-60
-    scal[0] = sg2;
+    a.scal[0] = sg2;
   }
 }
 
