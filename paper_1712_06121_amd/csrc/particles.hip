@@ -1356,9 +1356,11 @@ __device__ __forceinline__ void move_dense_tile(MoveArgs a, const unsigned lb) {
           peers &= bit ? bb : ~bb;
         }
         const uint32_t rin = lanes_below(peers), npeer = (uint32_t)__popcll(peers);
+        // the lowest lane of the key: it alone advances the key's running count
+        const int leader = peers ? __ffsll((long long)peers) - 1 : lane;
         // the ranks are formed before the turn is awaited (the compiler would otherwise move them
         // into the ordered section, which the chunks pass through one at a time)
-        asm volatile("" ::"v"(rin), "v"(npeer));
+        asm volatile("" ::"v"(rin), "v"(npeer), "v"(leader));
         // destination cell data, requested before the turn is awaited
         const int nx = wrapi(g.cx0 + ci + k[0], a.nc), ny = wrapi(g.cy0 + o1 + k[1], a.nc);
         const int nz = wrapi(g.cz0 + o2 + k[2], a.nc);
@@ -1386,10 +1388,12 @@ __device__ __forceinline__ void move_dense_tile(MoveArgs a, const unsigned lb) {
             }
           }
         }
+        // the ordered section: one LDS read-modify-write per key (by its lowest lane), then the turn
+        // passes on; the key's other lanes take the count from that lane afterwards
         uint32_t b0 = 0u;
-        if (active) b0 = grp[key];
-        if (active && rin == 0u) grp[key] = b0 + npeer;
+        if (active && rin == 0u) b0 = atomicAdd(&grp[key], npeer);
         if (lane == 0) __hip_atomic_store(&turn[0], chunk + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        b0 = (uint32_t)__shfl((int)b0, leader);
         if (active) {
           const uint64_t dst = dbase + b0 + rin;
           if (dst < (uint64_t)a.cap) {
